@@ -1,0 +1,214 @@
+/*
+ * pd.h -- C ABI of the MI355X-native curvilinear patch dynamics library (libpd.so).
+ *
+ * The scheme is that of Karmakar & Dalal, "A Generalised Curvilinear Coordinate
+ * system-based Patch Dynamics Scheme in Equation-free Multiscale Modelling"
+ * (arXiv 2405.08764):  the CDR equation eq. (Physical_Problem) is mapped to a rectangle
+ * (eq. Computational_Problem), patches sit on the interior nodes of an equidistant macro
+ * mesh (Sec. 3), and one macro step is steps (i)-(vi) of Sec. 3.3: Neumann edge data
+ * eq. (edge), lifting eq. (Lifting)/(C_0), a burst of explicit finite-difference nano
+ * steps inside every patch, the trapezoidal restriction eq. (Restriction), the time
+ * derivative eq. (Time_Derivative) and the projective step eq. (Extrapolation).
+ *
+ * Conventions for every call:
+ *  - Pointers named dev_* / U / Ubar / patch_state / edge are DEVICE pointers on the
+ *    grid's device; host_* pointers are host memory.  The caller owns all of them; the
+ *    library never allocates or frees caller memory.  The only device memory the library
+ *    uses beyond the arguments is the caller-provided workspace (pd_bind_workspace).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
+ *    except create/query/destroy/bind/get_* is asynchronous on that stream, except
+ *    pd_set_coefficients, which synchronises the stream once to read back the explicit
+ *    stability bounds.
+ *  - Macro fields U are FP64, row-major [n_eta][n_xi] (node (i, j) at j*n_xi + i).
+ *    Patch p sits on node (i, j) = (i_first + p % npx, 1 + p / npx) with npx patches per
+ *    row, i_first = 0 on a periodic xi axis and 1 otherwise.
+ *  - Micro fields are FP64 [P][m_eta][m_xi]; edge data FP64 [P][4][max(m_xi, m_eta)]
+ *    in the edge order (xi-, xi+, eta-, eta+).
+ *  - Return values: PD_OK or a negative pd_status; pd_last_error() gives a message
+ *    (thread-local).  No C++ exception crosses this interface.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pd_status;
+#define PD_OK 0
+#define PD_EINVAL (-1)      /* invalid descriptor or argument                          */
+#define PD_ESTATE (-2)      /* workspace or coefficients not set                       */
+#define PD_EUNSTABLE (-3)   /* time step above the explicit bound (see pd_set_option)  */
+#define PD_EDEVICE (-4)     /* HIP runtime error; message carries hipGetErrorString    */
+#define PD_ENONFINITE (-5)  /* a non-finite macro value was produced                   */
+#define PD_ENOMEM (-6)      /* workspace too small                                     */
+
+#define PD_MAXMODE 16
+#define PD_MAXPOLAR 4
+#define PD_MAXTERM 4
+
+/* Map x(xi, eta), y(xi, eta) of eq. (Transformtion_Inv). */
+#define PD_GEOM_IDENTITY 0 /* x = xi, y = eta                                           */
+#define PD_GEOM_SINE 1     /* eq. (Stretching_Transformation), box [0,1]^2, 0 <= l < 1  */
+#define PD_GEOM_TANH 2     /* x = tanh(b xi)/tanh(b), y likewise, box [0,1]^2, b >= 0    */
+#define PD_GEOM_ANNULUS 3  /* eq. (Transformation_Annulus): xi = theta (periodic),      */
+                           /* eta = r in [eta0, eta1], eta0 > 0                          */
+#define PD_CONV_UPWIND 0   /* 2-point upwind first differences (Sec. 4.1.1)            */
+#define PD_CONV_CENTRAL 1  /* central first differences (eq. MOL_Diff_Annu)            */
+#define PD_C0_TRAPEZOID 0  /* C0 consistent with the trapezoid restriction            */
+#define PD_C0_PRINTED 1    /* C0 with the printed h^2/24 of eq. (C_0)                  */
+#define PD_F64 0           /* burst arithmetic in FP64                                 */
+#define PD_F32 1           /* burst in FP32 on deviations from the patch's macro value */
+
+typedef struct {
+  int32_t geometry;
+  double gparam;                  /* lambda (sine) or beta (tanh)                      */
+  double xi0, xi1, eta0, eta1;    /* computational box Omega_c                         */
+  int32_t n_xi, n_eta;            /* macro node counts; periodic axis: unique nodes    */
+  int32_t periodic_xi;            /* 1: xi periodic (annulus), Sec. 4.2                */
+  double h_xi, h_eta;             /* patch edge lengths, 0 < h < Delta (Sec. 3)        */
+  int32_t m_xi, m_eta;            /* micro points per patch side incl. edges, 3..64    */
+  int32_t conv;                   /* PD_CONV_*                                          */
+  int32_t c0mode;                 /* PD_C0_*                                            */
+  int32_t precision;              /* PD_F64 / PD_F32                                    */
+  int32_t device;                 /* HIP device ordinal                                 */
+} pd_grid_desc;
+
+/* Scalar field F(x, y) = c0 + cx x + cy y + sum amp cos(kx x + ky y + ph)
+ *   + sum pamp (pc0 + pc1 r + pc2 r^2) cos(pn theta + pph)   (polar terms: annulus). */
+typedef struct {
+  double c0, cx, cy;
+  int32_t nmode;
+  double amp[PD_MAXMODE], kx[PD_MAXMODE], ky[PD_MAXMODE], ph[PD_MAXMODE];
+  int32_t npolar;
+  double pamp[PD_MAXPOLAR], pc0[PD_MAXPOLAR], pc1[PD_MAXPOLAR], pc2[PD_MAXPOLAR];
+  double pn[PD_MAXPOLAR], pph[PD_MAXPOLAR];
+} pd_field;
+
+/* 1-D function: SIN sin(a s + b), COS cos(a s + b), EXP exp(a s + b),
+ * POLY a + b s + c s^2 + d s^3. */
+#define PD_FN_SIN 0
+#define PD_FN_COS 1
+#define PD_FN_EXP 2
+#define PD_FN_POLY 3
+typedef struct { int32_t type; double a, b, c, d; } pd_fn1;
+/* kind 0: amp f(x) g(y);  kind 1 (annulus): amp f(r) g(theta). */
+typedef struct { int32_t kind; double amp; pd_fn1 f, g; } pd_sfun;
+/* Time factor: CONST a;  EXP a exp(b t);  SIN a + b sin(c t). */
+#define PD_T_CONST 0
+#define PD_T_EXP 1
+#define PD_T_SIN 2
+typedef struct { int32_t type; double a, b, c; } pd_tfun;
+
+/* eq. (Physical_Problem): u_t = div(D grad u - v u) + f u + g with D = diag(D11, D22)
+ * (D11 == D22 on the annulus), v = (v1, v2), reaction f.  Initial/Dirichlet data
+ * u_b = sum_m bc_t[m](t) bc_s[m](x, y); source g = sum_k src_t[k](t) (src_c[k] S_k - L[S_k])
+ * with S_k = src_s[k] and L the spatial operator (a manufactured solution T S has
+ * c = T'/T).  At most PD_MAXTERM terms each. */
+typedef struct {
+  pd_field D11, D22, v1, v2, f;
+  int32_t n_bc;
+  pd_tfun bc_t[PD_MAXTERM];
+  pd_sfun bc_s[PD_MAXTERM];
+  int32_t n_src;
+  pd_tfun src_t[PD_MAXTERM];
+  double src_c[PD_MAXTERM];
+  pd_sfun src_s[PD_MAXTERM];
+} pd_coeff_desc;
+
+typedef struct {
+  int32_t n_patches, m_xi, m_eta, n_xi, n_eta;
+  int64_t n_points;          /* n_patches * m_xi * m_eta                              */
+  size_t workspace_bytes;    /* device bytes pd_bind_workspace needs                  */
+  double dt_micro_limit;     /* explicit bound over micro points (after coefficients)  */
+  double dt_macro_limit;     /* explicit bound at macro spacing over patch nodes       */
+  int32_t coefficients_set;
+  int32_t n_time_sources;    /* source terms with a non-constant time factor           */
+  int32_t rows_per_lane, patches_per_block, block_threads; /* current launch shape     */
+} pd_info;
+
+typedef struct pd_grid_s* pd_grid;
+
+/* Sec. 3: build the macro mesh, the patch index map and the stencil tables (Lagrange
+ * weights eq. (Lagrange_2D) at the micro edge points, eq. (edge) weights, trapezoid
+ * weights, micro offsets) on the host.  Allocates no device memory.
+ * Errors: PD_EINVAL for out-of-range fields (h >= Delta, m < 3 or m > 64, n < 3, bad
+ * geometry or box), PD_EDEVICE if the device cannot be selected. */
+pd_status pd_create_grid(const pd_grid_desc* desc, pd_grid* out);
+pd_status pd_destroy_grid(pd_grid g);
+pd_status pd_query(pd_grid g, pd_info* out);
+/* Give the grid `bytes` of device memory at dev (>= pd_info.workspace_bytes, 256-byte
+ * aligned) for its coefficients, tables, ping-pong macro buffer and flags.  The memory
+ * must stay valid until the grid is destroyed or rebound.  PD_ENOMEM if too small. */
+pd_status pd_bind_workspace(pd_grid g, void* dev, size_t bytes);
+/* Sec. 2.1 coefficient list of eq. (Computational_Problem) (alpha, gamma, nu, omega,
+ * phi and the source parts) at every micro point, computed on the device in the
+ * scale-factor form for orthogonal maps; also the explicit stability bounds.
+ * PD_EINVAL on a bad descriptor or non-positive diffusion, PD_ESTATE without workspace. */
+pd_status pd_set_coefficients(pd_grid g, const pd_coeff_desc* c, void* stream);
+/* U at every node from u_b(t) (initial data, Sec. 3.2). */
+pd_status pd_initial(pd_grid g, double* U, double t, void* stream);
+
+/* Steps (i) and (ii) of Sec. 3.3: eq. (edge) gradients into edge [P][4][M] and the lifted
+ * micro field eq. (Lifting) into patch_state [P][m_eta][m_xi], both FP64. */
+pd_status pd_lift_bc(pd_grid g, const double* U, double* patch_state, double* edge,
+                     void* stream);
+/* Step (iii): n_t explicit forward-Euler nano steps of size dt_micro from time t_n inside
+ * every patch with the edge gradients held fixed (tau = n_t dt_micro).  patch_state is
+ * updated in place.  PD_EUNSTABLE if dt_micro exceeds the explicit bound. */
+pd_status pd_micro_burst(pd_grid g, double* patch_state, const double* edge, double t_n,
+                         double dt_micro, int32_t n_t, void* stream);
+/* Step (iv): eq. (Restriction) by the composite trapezoidal rule, Ubar[P]. */
+pd_status pd_restrict(pd_grid g, const double* patch_state, double* Ubar, void* stream);
+/* Steps (v)-(vi): U_np1 = U_n + dt_macro (Ubar - U_n)/tau at patch nodes, Dirichlet data
+ * at t_n + dt_macro on boundary nodes.  With Ubar == NULL the whole macro step (i)-(vi)
+ * runs fused on the device (the hot path).  U_n and U_np1 must not alias. */
+pd_status pd_macro_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
+                        double dt_macro, double dt_micro, int32_t n_t, const double* Ubar,
+                        void* stream);
+/* Steps (i)-(vi) fused on the device for the patch nodes only (U_np1's boundary nodes are
+ * left untouched); pd_macro_step with Ubar == NULL is this call followed by
+ * pd_apply_boundary.  U_n and U_np1 must not alias. */
+pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
+                        double dt_macro, double dt_micro, int32_t n_t, void* stream);
+/* Dirichlet data u_b(t) on every boundary node of U (eq. CDR_Com_IC_BCs, eq. Ann_C_IC_BCs:
+ * all four sides of a square, the two circles of the annulus). */
+pd_status pd_apply_boundary(pd_grid g, double* U, double t, void* stream);
+/* Repeat the fused macro step n_steps times from t0 (Sec. 3.3 "until the final time"),
+ * replayed from a captured HIP graph; U is in/out.  Runs on `stream` (a private stream
+ * ordered after the caller's when stream is NULL, since the null stream cannot be
+ * captured). */
+pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_steps,
+                   double dt_micro, int32_t n_t, void* stream);
+/* Synchronise the stream and report PD_ENONFINITE if a kernel saw a non-finite value
+ * since the last call (the flag is then cleared). */
+pd_status pd_sync(pd_grid g, void* stream);
+
+/* Host copies of the index map [P][11] (i, j, then the 9 node indices, eta offset outer)
+ * and of the stencil tables (same layout as documented in pd_get_tables_size). */
+pd_status pd_get_patch_map(pd_grid g, int32_t* host_out);
+/* Tables: s_xi[m_xi], s_eta[m_eta], L_q at the xi-edge points [m_eta][3], at the eta-edge
+ * points [m_xi][3], edge weights (xi-, xi+, eta-, eta+) x 3, trapezoid weights [m_xi],
+ * [m_eta], then Dxi, Deta, dxi, deta, r_xi, r_eta, kappa_xi, kappa_eta. */
+int32_t pd_get_tables_size(pd_grid g);
+pd_status pd_get_tables(pd_grid g, double* host_out);
+/* Device copy of the coefficient planes [5 + n_src][P][m_eta][m_xi] (alpha, gamma, nu,
+ * omega, phi, then each source term's spatial part in descriptor order). */
+pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
+
+/* Options: PD_OPT_ALLOW_UNSTABLE (0/1) skips the stability guard; PD_OPT_ROWS_PER_LANE
+ * and PD_OPT_PATCHES_PER_BLOCK set the burst launch shape (0 = automatic). */
+#define PD_OPT_ALLOW_UNSTABLE 1
+#define PD_OPT_ROWS_PER_LANE 2
+#define PD_OPT_PATCHES_PER_BLOCK 3
+pd_status pd_set_option(pd_grid g, int32_t option, int64_t value);
+
+const char* pd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -5,6 +5,8 @@
  *
  * Written from the paper; shares nothing with the HIP library.  Build:
  *   gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared pdo.c -o libpdo.so -lm
+ * and, for the extended-precision reference of the same steps,
+ *   gcc ... -DPDO_REAL="long double" pdo.c -o libpdo_ld.so -lm
  *
  * Parity pins (each checked by a CPU test against something other than this file):
  *   coefficients      Sec. 4.1.1, 4.1.2 and 4.2 closed-form coefficient lists
@@ -28,6 +30,14 @@
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* Arithmetic type of the edge data, lift, burst, restriction and projective step.  The
+ * default build is FP64; building with -DPDO_REAL="long double" gives the same algorithm
+ * in x87 extended precision, which measures the FP64 build's own round-off floor. */
+#ifndef PDO_REAL
+#define PDO_REAL double
+#endif
+typedef PDO_REAL real;
 
 static int g_threads = 1;
 
@@ -507,7 +517,7 @@ static int mmax(const pdo_grid* g) { return g->m_xi > g->m_eta ? g->m_xi : g->m_
 /* Gradients of the bi-quadratic interpolant of the 3x3 macro neighbourhood normal to the
  * four patch edges, at the micro points of each edge (kept fixed over the burst: the
  * Q = 1 case). */
-static void edge_patch(const pdo_grid* g, const double* U, int p, double* e) {
+static void edge_patch(const pdo_grid* g, const double* U, int p, real* e) {
   int i, j;
   patch_ij(g, p, &i, &j);
   int nx = g->n_xi, mx = g->m_xi, me = g->m_eta, M = mmax(g);
@@ -522,13 +532,13 @@ static void edge_patch(const pdo_grid* g, const double* U, int p, double* e) {
   for (int l = 0; l < me; ++l) {
     double t = micro_off(g->h_eta, me, l);
     double L[3] = {lagrange(0, t, De), lagrange(1, t, De), lagrange(2, t, De)};
-    double Pc[3];
+    real Pc[3];
     for (int a = 0; a < 3; ++a) {
-      Pc[a] = L[0] * U[(j - 1) * nx + ii[a]] + L[1] * U[j * nx + ii[a]] +
-              L[2] * U[(j + 1) * nx + ii[a]];
+      Pc[a] = (real)L[0] * U[(j - 1) * nx + ii[a]] + (real)L[1] * U[j * nx + ii[a]] +
+              (real)L[2] * U[(j + 1) * nx + ii[a]];
     }
-    e[0 * M + l] = (wm[0] * Pc[0] + wm[1] * Pc[1] + wm[2] * Pc[2]) / Dx;
-    e[1 * M + l] = (wp[0] * Pc[0] + wp[1] * Pc[1] + wp[2] * Pc[2]) / Dx;
+    e[0 * M + l] = ((real)wm[0] * Pc[0] + (real)wm[1] * Pc[1] + (real)wm[2] * Pc[2]) / Dx;
+    e[1 * M + l] = ((real)wp[0] * Pc[0] + (real)wp[1] * Pc[1] + (real)wp[2] * Pc[2]) / Dx;
   }
   /* eta edges: interpolate along xi (L_p^i) at every micro column. */
   edge_weights(re, -1, wm);
@@ -536,43 +546,49 @@ static void edge_patch(const pdo_grid* g, const double* U, int p, double* e) {
   for (int k = 0; k < mx; ++k) {
     double s = micro_off(g->h_xi, mx, k);
     double L[3] = {lagrange(0, s, Dx), lagrange(1, s, Dx), lagrange(2, s, Dx)};
-    double Pr[3];
+    real Pr[3];
     for (int b = 0; b < 3; ++b) {
       int jj = j - 1 + b;
-      Pr[b] = L[0] * U[jj * nx + im] + L[1] * U[jj * nx + i] + L[2] * U[jj * nx + ip];
+      Pr[b] = (real)L[0] * U[jj * nx + im] + (real)L[1] * U[jj * nx + i] +
+              (real)L[2] * U[jj * nx + ip];
     }
-    e[2 * M + k] = (wm[0] * Pr[0] + wm[1] * Pr[1] + wm[2] * Pr[2]) / De;
-    e[3 * M + k] = (wp[0] * Pr[0] + wp[1] * Pr[1] + wp[2] * Pr[2]) / De;
+    e[2 * M + k] = ((real)wm[0] * Pr[0] + (real)wm[1] * Pr[1] + (real)wm[2] * Pr[2]) / De;
+    e[3 * M + k] = ((real)wp[0] * Pr[0] + (real)wp[1] * Pr[1] + (real)wp[2] * Pr[2]) / De;
   }
 }
 
 void pdo_edge(const pdo_grid* g, const double* U, double* edge) {
   int P = pdo_num_patches(g), M = mmax(g);
-  for (int p = 0; p < P; ++p) edge_patch(g, U, p, edge + (size_t)p * 4 * M);
+  real* e = (real*)calloc(4 * M, sizeof(real)); /* entries past an edge's length stay 0 */
+  for (int p = 0; p < P; ++p) {
+    edge_patch(g, U, p, e);
+    for (int q = 0; q < 4 * M; ++q) edge[(size_t)p * 4 * M + q] = (double)e[q];
+  }
+  free(e);
 }
 
 /* ------------------------------------------------ step (ii): eq. (Lifting) -------- */
 
 /* Derivatives in eq. (Lifting) and eq. (C_0) by central differences at the node, which
  * are the derivatives of the bi-quadratic interpolant eq. (Lagrange_2D) there. */
-static void lift_patch(const pdo_grid* g, const double* U, int p, double* u) {
+static void lift_patch(const pdo_grid* g, const double* U, int p, real* u) {
   int i, j;
   patch_ij(g, p, &i, &j);
   int nx = g->n_xi, mx = g->m_xi, me = g->m_eta;
   double Dx = dxi(g), De = deta(g);
   int im = wrap_i(g, i - 1), ip = wrap_i(g, i + 1);
-  double Uc = U[j * nx + i];
-  double Ux = (U[j * nx + ip] - U[j * nx + im]) / (2.0 * Dx);
-  double Ue = (U[(j + 1) * nx + i] - U[(j - 1) * nx + i]) / (2.0 * De);
-  double Uxx = (U[j * nx + ip] - 2.0 * Uc + U[j * nx + im]) / (Dx * Dx);
-  double Uee = (U[(j + 1) * nx + i] - 2.0 * Uc + U[(j - 1) * nx + i]) / (De * De);
-  double Uxe = (U[(j + 1) * nx + ip] - U[(j - 1) * nx + ip] - U[(j + 1) * nx + im] +
-                U[(j - 1) * nx + im]) / (4.0 * Dx * De);
-  double C0 = Uc - kappa(g, g->h_xi, mx) * Uxx - kappa(g, g->h_eta, me) * Uee;
+  real Uc = U[j * nx + i];
+  real Ux = ((real)U[j * nx + ip] - U[j * nx + im]) / (2.0 * Dx);
+  real Ue = ((real)U[(j + 1) * nx + i] - U[(j - 1) * nx + i]) / (2.0 * De);
+  real Uxx = ((real)U[j * nx + ip] - 2.0 * Uc + U[j * nx + im]) / (Dx * Dx);
+  real Uee = ((real)U[(j + 1) * nx + i] - 2.0 * Uc + U[(j - 1) * nx + i]) / (De * De);
+  real Uxe = ((real)U[(j + 1) * nx + ip] - U[(j - 1) * nx + ip] - U[(j + 1) * nx + im] +
+              U[(j - 1) * nx + im]) / (4.0 * Dx * De);
+  real C0 = Uc - kappa(g, g->h_xi, mx) * Uxx - kappa(g, g->h_eta, me) * Uee;
   for (int l = 0; l < me; ++l) {
-    double t = micro_off(g->h_eta, me, l);
+    real t = micro_off(g->h_eta, me, l);
     for (int k = 0; k < mx; ++k) {
-      double s = micro_off(g->h_xi, mx, k);
+      real s = micro_off(g->h_xi, mx, k);
       u[l * mx + k] =
           C0 + s * Ux + t * Ue + 0.5 * s * s * Uxx + s * t * Uxe + 0.5 * t * t * Uee;
     }
@@ -582,7 +598,12 @@ static void lift_patch(const pdo_grid* g, const double* U, int p, double* u) {
 void pdo_lift(const pdo_grid* g, const double* U, double* u) {
   int P = pdo_num_patches(g);
   size_t pm = (size_t)g->m_xi * g->m_eta;
-  for (int p = 0; p < P; ++p) lift_patch(g, U, p, u + p * pm);
+  real* w = (real*)malloc(pm * sizeof(real));
+  for (int p = 0; p < P; ++p) {
+    lift_patch(g, U, p, w);
+    for (size_t q = 0; q < pm; ++q) u[p * pm + q] = (double)w[q];
+  }
+  free(w);
 }
 
 /* ----------------------------------------------- step (iii): the micro burst ------ */
@@ -595,22 +616,22 @@ void pdo_lift(const pdo_grid* g, const double* U, double* u) {
  * (u_m - u_{m-2})/(2 delta) = g^+, used by every difference that reaches past an edge;
  * corners take both ghosts independently.  Every point advances from the old level. */
 static int burst_patch(const pdo_grid* g, const pdo_problem* pr, const double* coef,
-                       size_t plane, int p, double* u, const double* e, double t_n, double dt,
-                       int n_t, double* w) {
+                       size_t plane, int p, real* u, const real* e, double t_n, double dt,
+                       int n_t, real* w) {
   int mx = g->m_xi, me = g->m_eta, M = mmax(g), nsrc = pr->n_src;
-  double dx = g->h_xi / (mx - 1), de = g->h_eta / (me - 1);
+  real dx = g->h_xi / (mx - 1), de = g->h_eta / (me - 1);
   size_t pm = (size_t)mx * me;
   const double* A = coef + 0 * plane + p * pm;
   const double* G = coef + 1 * plane + p * pm;
   const double* N = coef + 2 * plane + p * pm;
   const double* W = coef + 3 * plane + p * pm;
   const double* F = coef + 4 * plane + p * pm;
-  const double* gxm = e + 0 * M;
-  const double* gxp = e + 1 * M;
-  const double* gem = e + 2 * M;
-  const double* gep = e + 3 * M;
-  double* cur = u;
-  double* nxt = w;
+  const real* gxm = e + 0 * M;
+  const real* gxp = e + 1 * M;
+  const real* gem = e + 2 * M;
+  const real* gep = e + 3 * M;
+  real* cur = u;
+  real* nxt = w;
   for (int step = 0; step < n_t; ++step) {
     double t = t_n + step * dt;
     double T[PDO_MAXTERM];
@@ -618,14 +639,14 @@ static int burst_patch(const pdo_grid* g, const pdo_problem* pr, const double* c
     for (int l = 0; l < me; ++l)
       for (int k = 0; k < mx; ++k) {
         size_t at = (size_t)l * mx + k;
-        double uc = cur[at];
-        double uW = k > 0 ? cur[at - 1] : cur[at + 1] - 2.0 * dx * gxm[l];
-        double uE = k < mx - 1 ? cur[at + 1] : cur[at - 1] + 2.0 * dx * gxp[l];
-        double uS = l > 0 ? cur[at - mx] : cur[at + mx] - 2.0 * de * gem[k];
-        double uN = l < me - 1 ? cur[at + mx] : cur[at - mx] + 2.0 * de * gep[k];
-        double dxx = (uE - 2.0 * uc + uW) / (dx * dx);
-        double dee = (uN - 2.0 * uc + uS) / (de * de);
-        double nu = N[at], om = W[at], dx1, de1;
+        real uc = cur[at];
+        real uW = k > 0 ? cur[at - 1] : cur[at + 1] - 2.0 * dx * gxm[l];
+        real uE = k < mx - 1 ? cur[at + 1] : cur[at - 1] + 2.0 * dx * gxp[l];
+        real uS = l > 0 ? cur[at - mx] : cur[at + mx] - 2.0 * de * gem[k];
+        real uN = l < me - 1 ? cur[at + mx] : cur[at - mx] + 2.0 * de * gep[k];
+        real dxx = (uE - 2.0 * uc + uW) / (dx * dx);
+        real dee = (uN - 2.0 * uc + uS) / (de * de);
+        real nu = N[at], om = W[at], dx1, de1;
         if (g->conv == PDO_CONV_CENTRAL) {
           dx1 = (uE - uW) / (2.0 * dx);
           de1 = (uN - uS) / (2.0 * de);
@@ -633,12 +654,12 @@ static int burst_patch(const pdo_grid* g, const pdo_problem* pr, const double* c
           dx1 = nu >= 0.0 ? (uc - uW) / dx : (uE - uc) / dx;
           de1 = om >= 0.0 ? (uc - uS) / de : (uN - uc) / de;
         }
-        double src = 0.0;
-        for (int q = 0; q < nsrc; ++q) src += T[q] * coef[(5 + q) * plane + p * pm + at];
-        double rhs = A[at] * dxx + G[at] * dee - nu * dx1 - om * de1 + F[at] * uc + src;
-        nxt[at] = uc + dt * rhs;
+        real src = 0.0;
+        for (int q = 0; q < nsrc; ++q) src += (real)T[q] * coef[(5 + q) * plane + p * pm + at];
+        real rhs = A[at] * dxx + G[at] * dee - nu * dx1 - om * de1 + F[at] * uc + src;
+        nxt[at] = uc + (real)dt * rhs;
       }
-    double* tmp = cur;
+    real* tmp = cur;
     cur = nxt;
     nxt = tmp;
   }
@@ -657,11 +678,13 @@ int pdo_burst(const pdo_grid* g, const pdo_problem* pr, const double* coef, doub
   int bad = 0;
 #pragma omp parallel for schedule(static) num_threads(g_threads) reduction(+ : bad)
   for (int p = 0; p < P; ++p) {
-    double* w = (double*)malloc(pm * sizeof(double));
-    if (!burst_patch(g, pr, coef, plane, p, u + p * pm, edge + (size_t)p * 4 * M, t_n, dt, n_t,
-                     w))
-      bad++;
-    free(w);
+    real* v = (real*)malloc((2 * pm + 4 * M) * sizeof(real));
+    real* e = v + 2 * pm;
+    for (size_t q = 0; q < pm; ++q) v[q] = u[p * pm + q];
+    for (int q = 0; q < 4 * M; ++q) e[q] = edge[(size_t)p * 4 * M + q];
+    if (!burst_patch(g, pr, coef, plane, p, v, e, t_n, dt, n_t, v + pm)) bad++;
+    for (size_t q = 0; q < pm; ++q) u[p * pm + q] = (double)v[q];
+    free(v);
   }
   return bad ? PDO_ENONFINITE : PDO_OK;
 }
@@ -671,21 +694,26 @@ int pdo_burst(const pdo_grid* g, const pdo_problem* pr, const double* coef, doub
 /* Composite trapezoidal rule over the patch in the computational coordinates divided by
  * h_xi h_eta: weights 1/2 at the edges, the delta^2 factors cancel against
  * h = (m - 1) delta. */
-static double restrict_patch(const pdo_grid* g, const double* u) {
+static real restrict_patch(const pdo_grid* g, const real* u) {
   int mx = g->m_xi, me = g->m_eta;
-  double sum = 0.0;
+  real sum = 0.0;
   for (int l = 0; l < me; ++l) {
-    double row = 0.0;
+    real row = 0.0;
     for (int k = 0; k < mx; ++k) row += ((k == 0 || k == mx - 1) ? 0.5 : 1.0) * u[l * mx + k];
     sum += ((l == 0 || l == me - 1) ? 0.5 : 1.0) * row;
   }
-  return sum / ((double)(mx - 1) * (double)(me - 1));
+  return sum / ((real)(mx - 1) * (real)(me - 1));
 }
 
 void pdo_restrict(const pdo_grid* g, const double* u, double* Ubar) {
   int P = pdo_num_patches(g);
   size_t pm = (size_t)g->m_xi * g->m_eta;
-  for (int p = 0; p < P; ++p) Ubar[p] = restrict_patch(g, u + p * pm);
+  real* w = (real*)malloc(pm * sizeof(real));
+  for (int p = 0; p < P; ++p) {
+    for (size_t q = 0; q < pm; ++q) w[q] = u[p * pm + q];
+    Ubar[p] = (double)restrict_patch(g, w);
+  }
+  free(w);
 }
 
 /* ------------------------------- steps (v)-(vi): eq. (Time_Derivative), (Extrapolation) */
@@ -716,23 +744,23 @@ int pdo_step(const pdo_grid* g, const pdo_problem* pr, const double* coef, const
              double* Unp1, double t_n, double Dt, double dt, int n_t, const unsigned char* mask) {
   int P = pdo_num_patches(g), M = mmax(g), nx = g->n_xi;
   size_t pm = (size_t)g->m_xi * g->m_eta, plane = (size_t)P * pm;
-  double tau = n_t * dt;
+  real tau = n_t * dt;
   memcpy(Unp1, Un, sizeof(double) * (size_t)nx * g->n_eta);
   int bad = 0;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(g_threads) reduction(+ : bad)
   for (int p = 0; p < P; ++p) {
     if (mask && !mask[p]) continue;
-    double* u = (double*)malloc(2 * pm * sizeof(double) + 4 * M * sizeof(double));
-    double* w = u + pm;
-    double* e = w + pm;
+    real* u = (real*)malloc((2 * pm + 4 * M) * sizeof(real));
+    real* w = u + pm;
+    real* e = w + pm;
     edge_patch(g, Un, p, e);                                            /* (i)   */
     lift_patch(g, Un, p, u);                                            /* (ii)  */
     if (!burst_patch(g, pr, coef, plane, p, u, e, t_n, dt, n_t, w)) bad++; /* (iii) */
-    double Ub = restrict_patch(g, u);                                   /* (iv)  */
+    real Ub = restrict_patch(g, u);                                     /* (iv)  */
     int i, j;
     patch_ij(g, p, &i, &j);
-    double F = (Ub - Un[j * nx + i]) / tau;                             /* (v)   */
-    Unp1[j * nx + i] = Un[j * nx + i] + Dt * F;                         /* (vi)  */
+    real F = (Ub - Un[j * nx + i]) / tau;                               /* (v)   */
+    Unp1[j * nx + i] = (double)(Un[j * nx + i] + (real)Dt * F);         /* (vi)  */
     free(u);
   }
   set_boundary(g, pr, Unp1, t_n + Dt);

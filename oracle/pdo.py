@@ -15,6 +15,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpdo.so")
+LIB_LD_PATH = os.path.join(HERE, "libpdo_ld.so")
 SRC = os.path.join(HERE, "pdo.c")
 
 MAXMODE, MAXPOLAR, MAXTERM = 16, 4, 4
@@ -26,13 +27,15 @@ TF = {"const": 0, "exp": 1, "sin": 2}
 
 
 def build(force=False):
-    """Compile the oracle with gcc (-O2 -ffp-contract=off, OpenMP over patches)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
-            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "pdo.h"))):
-        tmp = LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
-                               "-shared", SRC, "-o", tmp, "-lm"], cwd=HERE)
-        os.replace(tmp, LIB_PATH)
+    """Compile the oracle with gcc (-O2 -ffp-contract=off, OpenMP over patches): the FP64
+    build and the same source in x87 extended precision (long double)."""
+    newest = max(os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "pdo.h")))
+    for path, extra in ((LIB_PATH, []), (LIB_LD_PATH, ["-DPDO_REAL=long double"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < newest:
+            tmp = path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+                                   "-shared", *extra, SRC, "-o", tmp, "-lm"], cwd=HERE)
+            os.replace(tmp, path)
     return LIB_PATH
 
 
@@ -74,16 +77,17 @@ class Problem(C.Structure):
                 ("src_s", Sfun * MAXTERM)]
 
 
-_lib = None
+_libs = {}
 _DP = C.POINTER(C.c_double)
 _IP = C.POINTER(C.c_int)
 
 
-def lib():
-    global _lib
-    if _lib is None:
+def lib(extended=False):
+    """The FP64 oracle, or with extended=True its long-double build."""
+    key = bool(extended)
+    if key not in _libs:
         build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(LIB_LD_PATH if key else LIB_PATH)
         GP, PP = C.POINTER(Grid), C.POINTER(Problem)
         sig = {
             "pdo_check": (C.c_int, [GP, PP]),
@@ -117,8 +121,8 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
-        _lib = L
-    return _lib
+        _libs[key] = L
+    return _libs[key]
 
 
 def _dp(a):
@@ -198,9 +202,9 @@ def make_problem(p):
 class Oracle:
     """The oracle on one problem dict (see ``paper_2405_08764_amd.workloads``)."""
 
-    def __init__(self, prob, threads=1):
+    def __init__(self, prob, threads=1, extended=False):
         self.prob = prob
-        self.L = lib()
+        self.L = lib(extended)
         self.g = make_grid(prob["grid"])
         self.p = make_problem(prob)
         self.G = C.byref(self.g)

@@ -1,0 +1,388 @@
+// Coefficients of the transformed operator, boundary data and explicit bounds.
+//
+// Sec. 2.1, eq. (Computational_Problem): for an orthogonal map (beta = 0) the operator
+// div(D grad u - v u) + f u becomes
+//   alpha u_xixi + gamma u_etaeta - nu u_xi - omega u_eta + phi u
+// and, with the scale factors h1 = |r_xi|, h2 = |r_eta| and D = diag(D11, D22),
+//   alpha = D11 / h1^2,  gamma = D22 / h2^2,
+//   nu    = (v . r_xi)  / h1^2 - d_xi (D11 h2 / h1) / (h1 h2),
+//   omega = (v . r_eta) / h2^2 - d_eta(D22 h1 / h2) / (h1 h2),
+//   phi   = f - div v,
+// which reproduces the worked lists of Sec. 4.1.1 (eq. P1_C), 4.1.2 (eq. P1_C_Vari_Diff)
+// and 4.2 (eq. Ann_Diff_Computational).  Maps: eq. (Stretching_Transformation),
+// tanh stretching clustered at x = 1, eq. (Transformation_Annulus) with xi = theta.
+// Source term k: T_k(t) (c_k S_k - L[S_k]), L the same operator applied to S_k.
+#include "pd_internal.h"
+
+namespace pdk {
+namespace {
+
+struct Metric {
+  double x, y;
+  double x_s, y_s, x_e, y_e;         // first derivatives (s = xi, e = eta)
+  double x_ss, y_ss, x_ee, y_ee;     // second derivatives
+  double x_se, y_se;                 // mixed
+};
+
+__device__ void metric_at(const Geo& g, double xi, double eta, Metric& m) {
+  m = Metric{};
+  if (g.geometry == PD_GEOM_SINE) {
+    const double l = g.gparam;
+    double sx, cx, se, ce;
+    sincospi(xi, &sx, &cx);
+    sincospi(eta, &se, &ce);
+    m.x = xi + (l / M_PI) * sx;
+    m.y = eta + (l / M_PI) * se;
+    m.x_s = 1.0 + l * cx;
+    m.y_e = 1.0 + l * ce;
+    m.x_ss = -l * M_PI * sx;
+    m.y_ee = -l * M_PI * se;
+  } else if (g.geometry == PD_GEOM_TANH && g.gparam != 0.0) {
+    const double b = g.gparam, tb = tanh(b);
+    const double tx = tanh(b * xi), ty = tanh(b * eta);
+    const double qx = 1.0 - tx * tx, qy = 1.0 - ty * ty;   // sech^2
+    m.x = tx / tb;
+    m.y = ty / tb;
+    m.x_s = b * qx / tb;
+    m.y_e = b * qy / tb;
+    m.x_ss = -2.0 * b * b * tx * qx / tb;
+    m.y_ee = -2.0 * b * b * ty * qy / tb;
+  } else if (g.geometry == PD_GEOM_ANNULUS) {
+    double s, c;
+    sincos(xi, &s, &c);
+    m.x = eta * c;
+    m.y = eta * s;
+    m.x_s = -eta * s;
+    m.y_s = eta * c;
+    m.x_e = c;
+    m.y_e = s;
+    m.x_ss = -eta * c;
+    m.y_ss = -eta * s;
+    m.x_se = -s;
+    m.y_se = c;
+  } else {
+    m.x = xi;
+    m.y = eta;
+    m.x_s = 1.0;
+    m.y_e = 1.0;
+  }
+}
+
+// Value and Cartesian gradient of a field; polar terms use r = eta, theta = xi.
+__device__ void field_at(const pd_field& F, double x, double y, bool annulus, double r,
+                         double th, double& v, double& vx, double& vy) {
+  v = F.c0 + F.cx * x + F.cy * y;
+  vx = F.cx;
+  vy = F.cy;
+  for (int k = 0; k < F.nmode; ++k) {
+    double s, c;
+    sincos(F.kx[k] * x + F.ky[k] * y + F.ph[k], &s, &c);
+    v += F.amp[k] * c;
+    vx -= F.amp[k] * F.kx[k] * s;
+    vy -= F.amp[k] * F.ky[k] * s;
+  }
+  if (annulus && F.npolar > 0) {
+    double st, ct;
+    sincos(th, &st, &ct);
+    for (int k = 0; k < F.npolar; ++k) {
+      const double P = F.pc0[k] + F.pc1[k] * r + F.pc2[k] * r * r;
+      const double dP = F.pc1[k] + 2.0 * F.pc2[k] * r;
+      double s, c;
+      sincos(F.pn[k] * th + F.pph[k], &s, &c);
+      const double fr = F.pamp[k] * dP * c;             // dF/dr
+      const double ft = -F.pamp[k] * P * F.pn[k] * s;   // dF/dtheta
+      v += F.pamp[k] * P * c;
+      vx += ct * fr - st / r * ft;
+      vy += st * fr + ct / r * ft;
+    }
+  }
+}
+
+__device__ void fn1_at(const pd_fn1& f, double s, double& v, double& d1, double& d2) {
+  if (f.type == PD_FN_SIN || f.type == PD_FN_COS) {
+    double sn, cs;
+    sincos(f.a * s + f.b, &sn, &cs);
+    if (f.type == PD_FN_SIN) {
+      v = sn;
+      d1 = f.a * cs;
+      d2 = -f.a * f.a * sn;
+    } else {
+      v = cs;
+      d1 = -f.a * sn;
+      d2 = -f.a * f.a * cs;
+    }
+  } else if (f.type == PD_FN_EXP) {
+    v = exp(f.a * s + f.b);
+    d1 = f.a * v;
+    d2 = f.a * f.a * v;
+  } else {
+    v = f.a + f.b * s + f.c * s * s + f.d * s * s * s;
+    d1 = f.b + 2.0 * f.c * s + 3.0 * f.d * s * s;
+    d2 = 2.0 * f.c + 6.0 * f.d * s;
+  }
+}
+
+// S and its derivatives in the computational coordinates: S, S_xi, S_eta, S_xixi, S_etaeta.
+__device__ void sfun_at(const pd_sfun& S, const Metric& m, double xi, double eta, double* o) {
+  double f, f1, f2, q, q1, q2;
+  if (S.kind == 1) {  // amp f(r) g(theta), r = eta, theta = xi
+    fn1_at(S.f, eta, f, f1, f2);
+    fn1_at(S.g, xi, q, q1, q2);
+    o[0] = S.amp * f * q;
+    o[1] = S.amp * f * q1;
+    o[2] = S.amp * f1 * q;
+    o[3] = S.amp * f * q2;
+    o[4] = S.amp * f2 * q;
+    return;
+  }
+  fn1_at(S.f, m.x, f, f1, f2);
+  fn1_at(S.g, m.y, q, q1, q2);
+  const double Sx = S.amp * f1 * q, Sy = S.amp * f * q1;
+  const double Sxx = S.amp * f2 * q, Syy = S.amp * f * q2, Sxy = S.amp * f1 * q1;
+  o[0] = S.amp * f * q;
+  o[1] = Sx * m.x_s + Sy * m.y_s;
+  o[2] = Sx * m.x_e + Sy * m.y_e;
+  o[3] = Sxx * m.x_s * m.x_s + 2.0 * Sxy * m.x_s * m.y_s + Syy * m.y_s * m.y_s + Sx * m.x_ss +
+         Sy * m.y_ss;
+  o[4] = Sxx * m.x_e * m.x_e + 2.0 * Sxy * m.x_e * m.y_e + Syy * m.y_e * m.y_e + Sx * m.x_ee +
+         Sy * m.y_ee;
+}
+
+__device__ double tfun_at(const pd_tfun& T, double t) {
+  if (T.type == PD_T_EXP) return T.a * exp(T.b * t);
+  if (T.type == PD_T_SIN) return T.a + T.b * sin(T.c * t);
+  return T.a;
+}
+
+// alpha, gamma, nu, omega, phi and the source parts at (xi, eta).
+__device__ void coefficients_at(const Geo& g, const pd_coeff_desc& c, int n_src, double xi,
+                                double eta, double* out) {
+  Metric m;
+  metric_at(g, xi, eta, m);
+  const bool ann = g.geometry == PD_GEOM_ANNULUS;
+  const double h1 = sqrt(m.x_s * m.x_s + m.y_s * m.y_s);
+  const double h2 = sqrt(m.x_e * m.x_e + m.y_e * m.y_e);
+  const double h1_s = (m.x_s * m.x_ss + m.y_s * m.y_ss) / h1;
+  const double h1_e = (m.x_s * m.x_se + m.y_s * m.y_se) / h1;
+  const double h2_s = (m.x_e * m.x_se + m.y_e * m.y_se) / h2;
+  const double h2_e = (m.x_e * m.x_ee + m.y_e * m.y_ee) / h2;
+  double a, ax, ay, b, bx, by, v1, v1x, v1y, v2, v2x, v2y, f, fx, fy;
+  field_at(c.D11, m.x, m.y, ann, eta, xi, a, ax, ay);
+  field_at(c.D22, m.x, m.y, ann, eta, xi, b, bx, by);
+  field_at(c.v1, m.x, m.y, ann, eta, xi, v1, v1x, v1y);
+  field_at(c.v2, m.x, m.y, ann, eta, xi, v2, v2x, v2y);
+  field_at(c.f, m.x, m.y, ann, eta, xi, f, fx, fy);
+  const double a_s = ax * m.x_s + ay * m.y_s;   // d D11 / d xi
+  const double b_e = bx * m.x_e + by * m.y_e;   // d D22 / d eta
+  const double alpha = a / (h1 * h1);
+  const double gamma = b / (h2 * h2);
+  const double nu = (v1 * m.x_s + v2 * m.y_s) / (h1 * h1) -
+                    (a_s * h2 / h1 + a * (h2_s * h1 - h2 * h1_s) / (h1 * h1)) / (h1 * h2);
+  const double omega = (v1 * m.x_e + v2 * m.y_e) / (h2 * h2) -
+                       (b_e * h1 / h2 + b * (h1_e * h2 - h1 * h2_e) / (h2 * h2)) / (h1 * h2);
+  const double phi = f - (v1x + v2y);
+  out[0] = alpha;
+  out[1] = gamma;
+  out[2] = nu;
+  out[3] = omega;
+  out[4] = phi;
+  for (int k = 0; k < n_src; ++k) {
+    double S[5];
+    sfun_at(c.src_s[k], m, xi, eta, S);
+    const double LS = alpha * S[3] + gamma * S[4] - nu * S[1] - omega * S[2] + phi * S[0];
+    out[5 + k] = c.src_c[k] * S[0] - LS;
+  }
+}
+
+__device__ double boundary_at(const Geo& g, const pd_coeff_desc& c, double xi, double eta,
+                              double t) {
+  Metric m;
+  metric_at(g, xi, eta, m);
+  double u = 0.0;
+  for (int q = 0; q < c.n_bc; ++q) {
+    double S[5];
+    sfun_at(c.bc_s[q], m, xi, eta, S);
+    u += tfun_at(c.bc_t[q], t) * S[0];
+  }
+  return u;
+}
+
+__device__ inline double micro_offset(double h, int m, int k) {
+  return (double)(2 * k - (m - 1)) * (h / (2.0 * (m - 1)));
+}
+
+__device__ inline void patch_node(const Geo& g, int p, int& i, int& j) {
+  i = g.i_first + p % g.npx;
+  j = 1 + p / g.npx;
+}
+
+__global__ void k_coefficients(Geo g, const pd_coeff_desc* __restrict__ desc, int n_src,
+                               double* __restrict__ coef) {
+  const long long npts = (long long)g.P * g.m_xi * g.m_eta;
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= npts) return;
+  const int pm = g.m_xi * g.m_eta;
+  const int p = (int)(q / pm), r = (int)(q - (long long)p * pm);
+  const int l = r / g.m_xi, k = r - l * g.m_xi;
+  int i, j;
+  patch_node(g, p, i, j);
+  const double xi = (g.xi0 + i * g.Dxi) + micro_offset(g.h_xi, g.m_xi, k);
+  const double eta = (g.eta0 + j * g.Deta) + micro_offset(g.h_eta, g.m_eta, l);
+  double out[5 + PD_MAXTERM];
+  coefficients_at(g, *desc, n_src, xi, eta, out);
+  for (int c = 0; c < 5 + n_src; ++c) coef[c * npts + q] = out[c];
+}
+
+__device__ inline double fe_bound(double a, double c, double nu, double om, double ph,
+                                  double dx, double de) {
+  return 1.0 / (2.0 * a / (dx * dx) + 2.0 * c / (de * de) + fabs(nu) / dx + fabs(om) / de +
+                fabs(ph));
+}
+
+// Block minima of the explicit forward-Euler bound over the micro points (slot 0) and
+// over the patch nodes at macro spacing (slot 1); 0 where diffusion is not positive.
+__global__ void k_limits(Geo g, const pd_coeff_desc* __restrict__ desc, int n_src,
+                         const double* __restrict__ coef, double* __restrict__ partial) {
+  __shared__ double red[2][256];
+  const long long npts = (long long)g.P * g.m_xi * g.m_eta;
+  double lo = INFINITY, hi = INFINITY;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < npts; q += stride) {
+    const double a = coef[q], c = coef[npts + q];
+    const double b = (a > 0.0 && c > 0.0)
+                         ? fe_bound(a, c, coef[2 * npts + q], coef[3 * npts + q],
+                                    coef[4 * npts + q], g.dxi, g.deta)
+                         : 0.0;
+    lo = fmin(lo, b);
+  }
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < g.P; p += stride) {
+    int i, j;
+    patch_node(g, (int)p, i, j);
+    double out[5 + PD_MAXTERM];
+    coefficients_at(g, *desc, 0, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, out);
+    const double b = (out[0] > 0.0 && out[1] > 0.0)
+                         ? fe_bound(out[0], out[1], out[2], out[3], out[4], g.Dxi, g.Deta)
+                         : 0.0;
+    hi = fmin(hi, b);
+  }
+  red[0][threadIdx.x] = lo;
+  red[1][threadIdx.x] = hi;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = red[0][0];
+    partial[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+__global__ void k_limits_final(const double* __restrict__ partial, int nblocks,
+                               double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double lo = INFINITY, hi = INFINITY;
+  for (int b = 0; b < nblocks; ++b) {
+    lo = fmin(lo, partial[2 * b]);
+    hi = fmin(hi, partial[2 * b + 1]);
+  }
+  out[0] = lo;
+  out[1] = hi;
+}
+
+__device__ inline bool is_boundary(const Geo& g, int i, int j) {
+  return j == 0 || j == g.n_eta - 1 || (!g.periodic && (i == 0 || i == g.n_xi - 1));
+}
+
+// Dirichlet data u_b(t) on the boundary nodes (eq. CDR_Com_IC_BCs, eq. Ann_C_IC_BCs).
+// One block; with a clock the time is t0 + (n + 1) dt and the clock advances afterwards.
+__global__ void k_boundary(Geo g, const pd_coeff_desc* __restrict__ desc, double* U, double t,
+                           Clock* clk, int advance) {
+  double* dst = U;
+  if (clk) {
+    const long long n = clk->n;
+    t = clk->t0 + (double)(n + 1) * clk->dt;
+    dst = clk->buf[(n + 1) & 1];
+  }
+  const int nb_rows = 2 * g.n_xi;                       // eta = eta0 and eta1 rows
+  const int nb_cols = g.periodic ? 0 : 2 * (g.n_eta - 2);
+  for (int q = threadIdx.x; q < nb_rows + nb_cols; q += blockDim.x) {
+    int i, j;
+    if (q < nb_rows) {
+      i = q % g.n_xi;
+      j = q < g.n_xi ? 0 : g.n_eta - 1;
+    } else {
+      const int r = q - nb_rows;
+      j = 1 + r / 2;
+      i = (r & 1) ? g.n_xi - 1 : 0;
+    }
+    dst[j * g.n_xi + i] = boundary_at(g, *desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, t);
+  }
+  if (clk && advance) {
+    __syncthreads();
+    if (threadIdx.x == 0) clk->n = clk->n + 1;
+  }
+}
+
+__global__ void k_initial(Geo g, const pd_coeff_desc* __restrict__ desc, double* U, double t) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.n_xi * g.n_eta) return;
+  const int j = q / g.n_xi, i = q - j * g.n_xi;
+  U[q] = boundary_at(g, *desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, t);
+}
+
+__global__ void k_clock_init(Clock* clk, double t0, double dt, double* b0, double* b1) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    clk->t0 = t0;
+    clk->dt = dt;
+    clk->n = 0;
+    clk->buf[0] = b0;
+    clk->buf[1] = b1;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_coefficients(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
+                               double* coef, hipStream_t s) {
+  const long long npts = (long long)g.P * g.m_xi * g.m_eta;
+  const int threads = 256;
+  const long long blocks = (npts + threads - 1) / threads;
+  hipLaunchKernelGGL(k_coefficients, dim3((unsigned)blocks), dim3(threads), 0, s, g, dev_desc,
+                     n_src, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_limits(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
+                         const double* coef, double* partial, int nblocks, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_limits, dim3(nblocks), dim3(256), 0, s, g, dev_desc, n_src, coef,
+                     partial);
+  hipLaunchKernelGGL(k_limits_final, dim3(1), dim3(64), 0, s, partial, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
+                           Clock* clk, int advance_clock, hipStream_t s) {
+  hipLaunchKernelGGL(k_boundary, dim3(1), dim3(256), 0, s, g, dev_desc, U, t, clk,
+                     advance_clock);
+  return hipGetLastError();
+}
+
+hipError_t launch_initial(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
+                          hipStream_t s) {
+  const int n = g.n_xi * g.n_eta;
+  hipLaunchKernelGGL(k_initial, dim3((n + 255) / 256), dim3(256), 0, s, g, dev_desc, U, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_init(Clock* clk, double t0, double dt, double* b0, double* b1,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_clock_init, dim3(1), dim3(64), 0, s, clk, t0, dt, b0, b1);
+  return hipGetLastError();
+}
+
+}  // namespace pdk

@@ -1,0 +1,694 @@
+// Host side of the C ABI in include/pd.h: validation, the macro mesh and patch index
+// map (Sec. 3), the stencil tables (eq. Lagrange_2D at the micro edge points, eq. edge
+// weights, trapezoid weights, the eq. C_0 constants), the caller-owned workspace, launch
+// shapes and the HIP graph that replays whole macro steps (Sec. 3.3 "until the final
+// time T").
+#pragma clang fp contract(off)
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pd_internal.h"
+
+namespace pdk {
+hipError_t launch_burst_f64(int R, int mode, const BurstArgs& a, int blocks, int threads,
+                            size_t lds, hipStream_t s);
+hipError_t launch_burst_f32(int R, int mode, const BurstArgs& a, int blocks, int threads,
+                            size_t lds, hipStream_t s);
+
+hipError_t launch_burst(int precision, int R, int mode, const BurstArgs& a, int blocks,
+                        int threads, size_t lds, hipStream_t s) {
+  return precision == PD_F32 ? launch_burst_f32(R, mode, a, blocks, threads, lds, s)
+                             : launch_burst_f64(R, mode, a, blocks, threads, lds, s);
+}
+
+bool burst_rows_supported(int R) {
+  return R == 3 || R == 4 || R == 5 || R == 6 || R == 7 || R == 8 || R == 9 || R == 11;
+}
+}  // namespace pdk
+
+using namespace pdk;
+
+namespace {
+
+thread_local std::string g_err;
+
+pd_status fail(pd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+pd_status hip_fail(hipError_t e, const char* where) {
+  return fail(PD_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+constexpr int NB_LIM = 512;  // blocks of the stability-bound reduction
+
+// Micro offsets: m points span the edge h symmetrically, edges included.
+double micro_off(double h, int m, int k) {
+  return (double)(2 * k - (m - 1)) * (h / (2.0 * (m - 1)));
+}
+
+// Lagrange basis eq. (Lagrange_2D) on the nodes (-D, 0, +D) relative to the patch centre:
+// product over the other nodes r in increasing order of (t - o_r) / (o_beta - o_r).
+double lagrange_basis(int beta, double t, double D) {
+  const double nodes[3] = {-D, 0.0, D};
+  double num = 0.0, den = 0.0;
+  bool started = false;
+  for (int r = 0; r < 3; ++r) {
+    if (r == beta) continue;
+    const double fn = t - nodes[r], fd = nodes[beta] - nodes[r];
+    if (!started) {
+      num = fn;
+      den = fd;
+      started = true;
+    } else {
+      num = num * fn;
+      den = den * fd;
+    }
+  }
+  return num / den;
+}
+
+}  // namespace
+
+struct pd_grid_s {
+  pd_grid_desc d{};
+  Geo g{};
+  std::vector<int32_t> pmap;
+  std::vector<double> tab;
+  TabOff to{};
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_coef = 0, off_pmap = 0, off_tab = 0, off_desc = 0, off_V = 0, off_flag = 0,
+         off_clock = 0, off_part = 0, off_lim = 0, need = 0;
+  // coefficients
+  bool coeffs_set = false;
+  pd_coeff_desc cd{};
+  int n_src = 0;
+  SrcInfo src{};
+  double lim_micro = 0.0, lim_macro = 0.0;
+  // options
+  int allow_unstable = 0, opt_R = 0, opt_ppb = 0;
+  // launch shape
+  int R = 0, ppb = 0, threads = 0, blocks = 0;
+  size_t lds = 0;
+  // graph replay of pd_solve
+  hipStream_t cap = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int g_steps = 0;
+  double g_dtm = 0, g_dt = 0;
+  int g_nt = 0;
+  double* g_U = nullptr;
+  int g_R = 0, g_ppb = 0;
+
+  double* coef() { return reinterpret_cast<double*>(ws + off_coef); }
+  int* dpmap() { return reinterpret_cast<int*>(ws + off_pmap); }
+  double* dtab() { return reinterpret_cast<double*>(ws + off_tab); }
+  pd_coeff_desc* ddesc() { return reinterpret_cast<pd_coeff_desc*>(ws + off_desc); }
+  double* V() { return reinterpret_cast<double*>(ws + off_V); }
+  int* flag() { return reinterpret_cast<int*>(ws + off_flag); }
+  Clock* clock() { return reinterpret_cast<Clock*>(ws + off_clock); }
+  double* part() { return reinterpret_cast<double*>(ws + off_part); }
+  double* lim() { return reinterpret_cast<double*>(ws + off_lim); }
+};
+
+namespace {
+
+void drop_graph(pd_grid g) {
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  g->gexec = nullptr;
+  g->graph = nullptr;
+  g->g_steps = 0;
+}
+
+// Launch shape of the burst: R rows per lane, ppb patches per 256-thread block, chosen for
+// the fewest idle lanes and padding rows (both are wasted VALU slots).
+void choose_shape(pd_grid g) {
+  const int mx = g->g.m_xi, me = g->g.m_eta;
+  int bestR = 0, bestP = 0;
+  double best = -1.0;
+  const int cand[] = {3, 4, 5, 6, 7, 8, 9, 11};
+  for (int R : cand) {
+    if (g->opt_R && R != g->opt_R) continue;
+    const int B = (me + R - 1) / R;
+    const int LP = mx * B;
+    if (LP > 256) continue;
+    int ppb = 256 / LP;
+    if (g->opt_ppb) ppb = g->opt_ppb < ppb ? g->opt_ppb : ppb;
+    const int threads = ((ppb * LP + 63) / 64) * 64;
+    if (burst_lds_bytes(g->d.precision, ppb, mx, me, g->src.ns) > 65536) continue;
+    const double eff = (double)ppb * mx * me / ((double)threads * R);
+    if (eff > best + 1e-9) {
+      best = eff;
+      bestR = R;
+      bestP = ppb;
+    }
+  }
+  g->R = bestR;
+  g->ppb = bestP;
+  if (bestR) {
+    const int LP = mx * ((me + bestR - 1) / bestR);
+    g->threads = ((bestP * LP + 63) / 64) * 64;
+    g->blocks = (g->g.P + bestP - 1) / bestP;
+    g->lds = burst_lds_bytes(g->d.precision, bestP, mx, me, g->src.ns);
+  }
+}
+
+pd_status check_field(const pd_field& f, bool annulus, const char* name) {
+  if (f.nmode < 0 || f.nmode > PD_MAXMODE || f.npolar < 0 || f.npolar > PD_MAXPOLAR)
+    return fail(PD_EINVAL, std::string(name) + ": term count out of range");
+  if (f.npolar > 0 && !annulus)
+    return fail(PD_EINVAL, std::string(name) + ": polar terms need the annulus geometry");
+  return PD_OK;
+}
+
+pd_status check_fn1(const pd_fn1& f) {
+  if (f.type < PD_FN_SIN || f.type > PD_FN_POLY) return fail(PD_EINVAL, "bad 1-D function type");
+  return PD_OK;
+}
+
+pd_status check_tfun(const pd_tfun& t) {
+  if (t.type < PD_T_CONST || t.type > PD_T_SIN) return fail(PD_EINVAL, "bad time factor type");
+  return PD_OK;
+}
+
+pd_status check_sfun(const pd_sfun& s, bool annulus) {
+  if (s.kind != 0 && s.kind != 1) return fail(PD_EINVAL, "bad spatial function kind");
+  if (s.kind == 1 && !annulus) return fail(PD_EINVAL, "polar spatial function needs the annulus");
+  pd_status st = check_fn1(s.f);
+  if (st) return st;
+  return check_fn1(s.g);
+}
+
+pd_status need_ws(pd_grid g) {
+  if (!g) return fail(PD_EINVAL, "null grid");
+  if (!g->ws) return fail(PD_ESTATE, "no workspace bound");
+  return PD_OK;
+}
+
+pd_status need_coeffs(pd_grid g) {
+  pd_status s = need_ws(g);
+  if (s) return s;
+  if (!g->coeffs_set) return fail(PD_ESTATE, "coefficients not set");
+  if (!g->R) return fail(PD_EINVAL, "no supported burst launch shape for this patch size");
+  return PD_OK;
+}
+
+pd_status guard_micro(pd_grid g, double dt, int n_t) {
+  if (!(dt > 0.0) || n_t < 1) return fail(PD_EINVAL, "dt_micro must be > 0 and n_t >= 1");
+  if (!g->allow_unstable && dt > g->lim_micro * (1.0 + 1e-12)) {
+    char b[160];
+    snprintf(b, sizeof b, "dt_micro %.6g above the explicit bound %.6g", dt, g->lim_micro);
+    return fail(PD_EUNSTABLE, b);
+  }
+  return PD_OK;
+}
+
+pd_status guard_macro(pd_grid g, double dtm, double dt, int n_t) {
+  pd_status s = guard_micro(g, dt, n_t);
+  if (s) return s;
+  if (!(dtm > 0.0)) return fail(PD_EINVAL, "dt_macro must be > 0");
+  if (!g->allow_unstable && dtm > g->lim_macro * (1.0 + 1e-12)) {
+    char b[160];
+    snprintf(b, sizeof b, "dt_macro %.6g above the explicit bound %.6g", dtm, g->lim_macro);
+    return fail(PD_EUNSTABLE, b);
+  }
+  return PD_OK;
+}
+
+BurstArgs base_args(pd_grid g, double t_n, double dt, int n_t) {
+  BurstArgs a{};
+  a.g = g->g;
+  a.src = g->src;
+  a.coef = g->coef();
+  a.pmap = g->dpmap();
+  a.tab = g->dtab();
+  a.plane = (long long)g->g.P * g->g.m_xi * g->g.m_eta;
+  a.t_n = t_n;
+  a.dt = dt;
+  a.n_t = n_t;
+  a.ppb = g->ppb;
+  a.flag = g->flag();
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pd_last_error(void) { return g_err.c_str(); }
+
+pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
+  if (!d || !out) return fail(PD_EINVAL, "null argument");
+  *out = nullptr;
+  const pd_grid_desc& D = *d;
+  if (D.n_xi < 3 || D.n_eta < 3) return fail(PD_EINVAL, "need at least 3 macro nodes per axis");
+  if (D.m_xi < 3 || D.m_eta < 3 || D.m_xi > 64 || D.m_eta > 64)
+    return fail(PD_EINVAL, "micro points per side must be in 3..64");
+  if (!(D.xi1 > D.xi0) || !(D.eta1 > D.eta0)) return fail(PD_EINVAL, "empty computational box");
+  const double Dxi = D.periodic_xi ? (D.xi1 - D.xi0) / D.n_xi : (D.xi1 - D.xi0) / (D.n_xi - 1);
+  const double Deta = (D.eta1 - D.eta0) / (D.n_eta - 1);
+  if (!(D.h_xi > 0.0) || !(D.h_eta > 0.0) || !(D.h_xi < Dxi) || !(D.h_eta < Deta))
+    return fail(PD_EINVAL, "patch edges must satisfy 0 < h < Delta (patches may not overlap)");
+  if (D.conv != PD_CONV_UPWIND && D.conv != PD_CONV_CENTRAL) return fail(PD_EINVAL, "bad conv");
+  if (D.c0mode != PD_C0_TRAPEZOID && D.c0mode != PD_C0_PRINTED) return fail(PD_EINVAL, "bad c0mode");
+  if (D.precision != PD_F64 && D.precision != PD_F32) return fail(PD_EINVAL, "bad precision");
+  const bool box01 = D.xi0 == 0.0 && D.xi1 == 1.0 && D.eta0 == 0.0 && D.eta1 == 1.0;
+  switch (D.geometry) {
+    case PD_GEOM_IDENTITY: break;
+    case PD_GEOM_SINE:
+      if (!box01 || !(D.gparam >= 0.0 && D.gparam < 1.0))
+        return fail(PD_EINVAL, "sine stretching needs the unit box and 0 <= lambda < 1");
+      break;
+    case PD_GEOM_TANH:
+      if (!box01 || !(D.gparam >= 0.0)) return fail(PD_EINVAL, "tanh stretching needs the unit box and beta >= 0");
+      break;
+    case PD_GEOM_ANNULUS:
+      if (!(D.eta0 > 0.0) || !D.periodic_xi)
+        return fail(PD_EINVAL, "the annulus needs eta0 > 0 and a periodic xi axis");
+      break;
+    default: return fail(PD_EINVAL, "bad geometry");
+  }
+  if (D.device < 0) return fail(PD_EINVAL, "negative device ordinal");
+
+  pd_grid g = new pd_grid_s();
+  g->d = D;
+  Geo& G = g->g;
+  G.geometry = D.geometry;
+  G.gparam = D.gparam;
+  G.xi0 = D.xi0; G.xi1 = D.xi1; G.eta0 = D.eta0; G.eta1 = D.eta1;
+  G.n_xi = D.n_xi; G.n_eta = D.n_eta; G.periodic = D.periodic_xi ? 1 : 0;
+  G.h_xi = D.h_xi; G.h_eta = D.h_eta;
+  G.m_xi = D.m_xi; G.m_eta = D.m_eta;
+  G.conv = D.conv; G.c0mode = D.c0mode;
+  G.Dxi = Dxi;
+  G.Deta = Deta;
+  G.dxi = D.h_xi / (D.m_xi - 1);
+  G.deta = D.h_eta / (D.m_eta - 1);
+  // eq. (C_0): C0 = U - kappa U_xixi - kappa U_etaeta; the trapezoid reading adds
+  // delta^2/12 so that the trapezoidal restriction of the lift returns U.
+  G.kap_xi = D.c0mode == PD_C0_PRINTED ? D.h_xi * D.h_xi / 24.0
+                                       : D.h_xi * D.h_xi / 24.0 + G.dxi * G.dxi / 12.0;
+  G.kap_eta = D.c0mode == PD_C0_PRINTED ? D.h_eta * D.h_eta / 24.0
+                                        : D.h_eta * D.h_eta / 24.0 + G.deta * G.deta / 12.0;
+  G.npx = D.periodic_xi ? D.n_xi : D.n_xi - 2;
+  G.i_first = D.periodic_xi ? 0 : 1;
+  G.P = G.npx * (D.n_eta - 2);
+  G.M = D.m_xi > D.m_eta ? D.m_xi : D.m_eta;
+
+  // Patch index map: node (i, j) and its 3x3 neighbourhood, wrapped on a periodic axis.
+  g->pmap.resize((size_t)G.P * 11);
+  for (int p = 0; p < G.P; ++p) {
+    const int i = G.i_first + p % G.npx, j = 1 + p / G.npx;
+    int32_t* o = &g->pmap[(size_t)p * 11];
+    o[0] = i;
+    o[1] = j;
+    for (int b = -1; b <= 1; ++b)
+      for (int a = -1; a <= 1; ++a) {
+        int ii = i + a;
+        if (D.periodic_xi) ii = (ii + D.n_xi) % D.n_xi;
+        o[2 + 3 * (b + 1) + (a + 1)] = (j + b) * D.n_xi + ii;
+      }
+  }
+
+  // Stencil tables.
+  const int mx = D.m_xi, me = D.m_eta;
+  g->to = tab_off(mx, me);
+  g->tab.assign(g->to.size, 0.0);
+  double* T = g->tab.data();
+  for (int k = 0; k < mx; ++k) T[g->to.s_xi + k] = micro_off(D.h_xi, mx, k);
+  for (int l = 0; l < me; ++l) T[g->to.s_eta + l] = micro_off(D.h_eta, me, l);
+  for (int l = 0; l < me; ++l)
+    for (int q = 0; q < 3; ++q) T[g->to.L_xe + 3 * l + q] = lagrange_basis(q, micro_off(D.h_eta, me, l), Deta);
+  for (int k = 0; k < mx; ++k)
+    for (int q = 0; q < 3; ++q) T[g->to.L_ee + 3 * k + q] = lagrange_basis(q, micro_off(D.h_xi, mx, k), Dxi);
+  const double rx = D.h_xi / (2.0 * Dxi), re = D.h_eta / (2.0 * Deta);
+  const double ew[12] = {-0.5 - rx, 2.0 * rx, 0.5 - rx, -0.5 + rx, -2.0 * rx, 0.5 + rx,
+                         -0.5 - re, 2.0 * re, 0.5 - re, -0.5 + re, -2.0 * re, 0.5 + re};
+  for (int q = 0; q < 12; ++q) T[g->to.ew + q] = ew[q];
+  for (int k = 0; k < mx; ++k) T[g->to.c_xi + k] = (k == 0 || k == mx - 1) ? 0.5 : 1.0;
+  for (int l = 0; l < me; ++l) T[g->to.c_eta + l] = (l == 0 || l == me - 1) ? 0.5 : 1.0;
+  const double sc[8] = {Dxi, Deta, G.dxi, G.deta, rx, re, G.kap_xi, G.kap_eta};
+  for (int q = 0; q < 8; ++q) T[g->to.scal + q] = sc[q];
+
+  // Workspace layout.
+  size_t o = 0;
+  const size_t npts = (size_t)G.P * mx * me;
+  g->off_coef = o; o = align256(o + (5 + PD_MAXTERM) * npts * sizeof(double));
+  g->off_pmap = o; o = align256(o + g->pmap.size() * sizeof(int32_t));
+  g->off_tab = o; o = align256(o + g->tab.size() * sizeof(double));
+  g->off_desc = o; o = align256(o + sizeof(pd_coeff_desc));
+  g->off_V = o; o = align256(o + (size_t)D.n_xi * D.n_eta * sizeof(double));
+  g->off_flag = o; o = align256(o + 16);
+  g->off_clock = o; o = align256(o + sizeof(Clock));
+  g->off_part = o; o = align256(o + 2 * NB_LIM * sizeof(double));
+  g->off_lim = o; o = align256(o + 2 * sizeof(double));
+  g->need = o;
+  choose_shape(g);
+  *out = g;
+  return PD_OK;
+}
+
+pd_status pd_destroy_grid(pd_grid g) {
+  if (!g) return PD_OK;
+  (void)hipSetDevice(g->d.device);
+  drop_graph(g);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  if (g->ev_in) (void)hipEventDestroy(g->ev_in);
+  if (g->ev_out) (void)hipEventDestroy(g->ev_out);
+  delete g;
+  return PD_OK;
+}
+
+pd_status pd_query(pd_grid g, pd_info* out) {
+  if (!g || !out) return fail(PD_EINVAL, "null argument");
+  pd_info& I = *out;
+  I = pd_info{};
+  I.n_patches = g->g.P;
+  I.m_xi = g->g.m_xi;
+  I.m_eta = g->g.m_eta;
+  I.n_xi = g->g.n_xi;
+  I.n_eta = g->g.n_eta;
+  I.n_points = (int64_t)g->g.P * g->g.m_xi * g->g.m_eta;
+  I.workspace_bytes = g->need;
+  I.dt_micro_limit = g->lim_micro;
+  I.dt_macro_limit = g->lim_macro;
+  I.coefficients_set = g->coeffs_set ? 1 : 0;
+  I.n_time_sources = g->src.ns;
+  I.rows_per_lane = g->R;
+  I.patches_per_block = g->ppb;
+  I.block_threads = g->threads;
+  return PD_OK;
+}
+
+pd_status pd_bind_workspace(pd_grid g, void* dev, size_t bytes) {
+  if (!g || !dev) return fail(PD_EINVAL, "null argument");
+  if (bytes < g->need) return fail(PD_ENOMEM, "workspace smaller than pd_info.workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(PD_EINVAL, "workspace must be 256-byte aligned");
+  HIPCHK(hipSetDevice(g->d.device));
+  drop_graph(g);
+  g->ws = static_cast<char*>(dev);
+  g->ws_bytes = bytes;
+  g->coeffs_set = false;
+  HIPCHK(hipMemcpy(g->dpmap(), g->pmap.data(), g->pmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(g->dtab(), g->tab.data(), g->tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(g->flag(), 0, 16));
+  return PD_OK;
+}
+
+pd_status pd_set_coefficients(pd_grid g, const pd_coeff_desc* c, void* stream) {
+  pd_status st = need_ws(g);
+  if (st) return st;
+  if (!c) return fail(PD_EINVAL, "null coefficient descriptor");
+  const bool ann = g->d.geometry == PD_GEOM_ANNULUS;
+  if ((st = check_field(c->D11, ann, "D11")) || (st = check_field(c->D22, ann, "D22")) ||
+      (st = check_field(c->v1, ann, "v1")) || (st = check_field(c->v2, ann, "v2")) ||
+      (st = check_field(c->f, ann, "f")))
+    return st;
+  if (ann && std::memcmp(&c->D11, &c->D22, sizeof(pd_field)) != 0)
+    return fail(PD_EINVAL, "the annulus takes a scalar diffusion coefficient (D11 == D22)");
+  if (c->n_bc < 0 || c->n_bc > PD_MAXTERM || c->n_src < 0 || c->n_src > PD_MAXTERM)
+    return fail(PD_EINVAL, "term count out of range");
+  SrcInfo si{};
+  for (int q = 0; q < c->n_bc; ++q)
+    if ((st = check_tfun(c->bc_t[q])) || (st = check_sfun(c->bc_s[q], ann))) return st;
+  for (int k = 0; k < c->n_src; ++k) {
+    if ((st = check_tfun(c->src_t[k])) || (st = check_sfun(c->src_s[k], ann))) return st;
+    if (c->src_t[k].type == PD_T_CONST) {
+      si.plane_c[si.nconst] = 5 + k;
+      si.ca[si.nconst] = c->src_t[k].a;
+      si.nconst++;
+    } else {
+      if (si.ns == 2) return fail(PD_EINVAL, "at most 2 time-dependent source terms");
+      si.plane_t[si.ns] = 5 + k;
+      si.ttype[si.ns] = c->src_t[k].type;
+      si.ta[si.ns] = c->src_t[k].a;
+      si.tb[si.ns] = c->src_t[k].b;
+      si.tc[si.ns] = c->src_t[k].c;
+      si.ns++;
+    }
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(g->d.device));
+  drop_graph(g);
+  HIPCHK(hipMemcpyAsync(g->ddesc(), c, sizeof(pd_coeff_desc), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_coefficients(g->g, g->ddesc(), c->n_src, g->coef(), s));
+  HIPCHK(launch_limits(g->g, g->ddesc(), c->n_src, g->coef(), g->part(), NB_LIM, g->lim(), s));
+  double lim[2];
+  HIPCHK(hipMemcpyAsync(lim, g->lim(), sizeof lim, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!(lim[0] > 0.0) || !(lim[1] > 0.0))
+    return fail(PD_EINVAL, "diffusion must be positive at every micro point and patch node");
+  g->cd = *c;
+  g->n_src = c->n_src;
+  g->src = si;
+  g->lim_micro = lim[0];
+  g->lim_macro = lim[1];
+  g->coeffs_set = true;
+  choose_shape(g);
+  return PD_OK;
+}
+
+pd_status pd_initial(pd_grid g, double* U, double t, void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U) return fail(PD_EINVAL, "null U");
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_initial(g->g, g->ddesc(), U, t, static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_lift_bc(pd_grid g, const double* U, double* state, double* edge, void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U || !state || !edge) return fail(PD_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_lift_bc(g->g, g->dpmap(), g->dtab(), U, state, edge,
+                        static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_micro_burst(pd_grid g, double* state, const double* edge, double t_n, double dt,
+                         int32_t n_t, void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!state || !edge) return fail(PD_EINVAL, "null argument");
+  if ((st = guard_micro(g, dt, n_t))) return st;
+  HIPCHK(hipSetDevice(g->d.device));
+  BurstArgs a = base_args(g, t_n, dt, n_t);
+  a.state = state;
+  a.edge = edge;
+  HIPCHK(launch_burst(g->d.precision, g->R, MODE_SPLIT, a, g->blocks, g->threads, g->lds,
+                      static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_restrict(pd_grid g, const double* state, double* Ubar, void* stream) {
+  pd_status st = need_ws(g);
+  if (st) return st;
+  if (!state || !Ubar) return fail(PD_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_restrict(g->g, state, Ubar, static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_macro_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
+                        double dt_macro, double dt, int32_t n_t, const double* Ubar,
+                        void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U_n || !U_np1 || U_n == U_np1) return fail(PD_EINVAL, "U_n, U_np1 must be distinct non-null buffers");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(g->d.device));
+  const double tau = n_t * dt;
+  if (Ubar) {
+    if (!(dt_macro > 0.0) || !(tau > 0.0)) return fail(PD_EINVAL, "dt_macro and tau must be > 0");
+    HIPCHK(launch_macro_update(g->g, g->dpmap(), U_n, Ubar, U_np1, dt_macro, tau, g->flag(), s));
+  } else {
+    if ((st = guard_macro(g, dt_macro, dt, n_t))) return st;
+    BurstArgs a = base_args(g, t_n, dt, n_t);
+    a.U = U_n;
+    a.Unew = U_np1;
+    a.dt_macro = dt_macro;
+    a.tau = tau;
+    HIPCHK(launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads, g->lds, s));
+  }
+  HIPCHK(launch_boundary(g->g, g->ddesc(), U_np1, t_n + dt_macro, nullptr, 0, s));
+  return PD_OK;
+}
+
+pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
+                        double dt_macro, double dt, int32_t n_t, void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U_n || !U_np1 || U_n == U_np1) return fail(PD_EINVAL, "U_n, U_np1 must be distinct non-null buffers");
+  if ((st = guard_macro(g, dt_macro, dt, n_t))) return st;
+  HIPCHK(hipSetDevice(g->d.device));
+  BurstArgs a = base_args(g, t_n, dt, n_t);
+  a.U = U_n;
+  a.Unew = U_np1;
+  a.dt_macro = dt_macro;
+  a.tau = n_t * dt;
+  HIPCHK(launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads, g->lds,
+                      static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_apply_boundary(pd_grid g, double* U, double t, void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U) return fail(PD_EINVAL, "null U");
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_boundary(g->g, g->ddesc(), U, t, nullptr, 0, static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_steps,
+                   double dt, int32_t n_t, void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U || n_steps < 0) return fail(PD_EINVAL, "null U or negative step count");
+  if (n_steps == 0) return PD_OK;
+  if ((st = guard_macro(g, dt_macro, dt, n_t))) return st;
+  HIPCHK(hipSetDevice(g->d.device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool own = s == nullptr;  // the null stream cannot be captured
+  if (own && !g->cap) {
+    HIPCHK(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+  }
+  hipStream_t w = own ? g->cap : s;
+  const double tau = n_t * dt;
+  BurstArgs a = base_args(g, t0, dt, n_t);
+  a.dt_macro = dt_macro;
+  a.tau = tau;
+  a.clk = g->clock();
+  const int S = n_steps < 16 ? n_steps : 16;  // macro steps per graph replay
+  const bool reuse = g->gexec && g->g_steps == S && g->g_dtm == dt_macro && g->g_dt == dt &&
+                     g->g_nt == n_t && g->g_U == U && g->g_R == g->R && g->g_ppb == g->ppb;
+  if (own) {
+    HIPCHK(hipEventRecord(g->ev_in, s));
+    HIPCHK(hipStreamWaitEvent(w, g->ev_in, 0));
+  }
+  HIPCHK(launch_clock_init(g->clock(), t0, dt_macro, U, g->V(), w));
+  if (!reuse) {
+    drop_graph(g);
+    HIPCHK(hipStreamBeginCapture(w, hipStreamCaptureModeThreadLocal));
+    for (int q = 0; q < S; ++q) {
+      hipError_t e1 = launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads,
+                                   g->lds, w);
+      hipError_t e2 = launch_boundary(g->g, g->ddesc(), nullptr, 0.0, g->clock(), 1, w);
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(w, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        return hip_fail(e1 != hipSuccess ? e1 : e2, "graph capture");
+      }
+    }
+    HIPCHK(hipStreamEndCapture(w, &g->graph));
+    HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
+    g->g_steps = S;
+    g->g_dtm = dt_macro;
+    g->g_dt = dt;
+    g->g_nt = n_t;
+    g->g_U = U;
+    g->g_R = g->R;
+    g->g_ppb = g->ppb;
+  }
+  const int reps = n_steps / S, rem = n_steps - reps * S;
+  for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(g->gexec, w));
+  for (int q = 0; q < rem; ++q) {
+    HIPCHK(launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads, g->lds, w));
+    HIPCHK(launch_boundary(g->g, g->ddesc(), nullptr, 0.0, g->clock(), 1, w));
+  }
+  if (n_steps & 1)
+    HIPCHK(hipMemcpyAsync(U, g->V(), (size_t)g->g.n_xi * g->g.n_eta * sizeof(double),
+                          hipMemcpyDeviceToDevice, w));
+  if (own) {
+    HIPCHK(hipEventRecord(g->ev_out, w));
+    HIPCHK(hipStreamWaitEvent(s, g->ev_out, 0));
+  }
+  return PD_OK;
+}
+
+pd_status pd_sync(pd_grid g, void* stream) {
+  pd_status st = need_ws(g);
+  if (st) return st;
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  int flag = 0;
+  HIPCHK(hipMemcpy(&flag, g->flag(), sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    HIPCHK(hipMemset(g->flag(), 0, sizeof(int)));
+    return fail(PD_ENONFINITE, "a kernel produced a non-finite value");
+  }
+  return PD_OK;
+}
+
+pd_status pd_get_patch_map(pd_grid g, int32_t* out) {
+  if (!g || !out) return fail(PD_EINVAL, "null argument");
+  std::memcpy(out, g->pmap.data(), g->pmap.size() * sizeof(int32_t));
+  return PD_OK;
+}
+
+int32_t pd_get_tables_size(pd_grid g) { return g ? g->to.size : 0; }
+
+pd_status pd_get_tables(pd_grid g, double* out) {
+  if (!g || !out) return fail(PD_EINVAL, "null argument");
+  std::memcpy(out, g->tab.data(), g->tab.size() * sizeof(double));
+  return PD_OK;
+}
+
+pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!dev_out) return fail(PD_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(g->d.device));
+  const size_t n = (size_t)(5 + g->n_src) * g->g.P * g->g.m_xi * g->g.m_eta;
+  HIPCHK(hipMemcpyAsync(dev_out, g->coef(), n * sizeof(double), hipMemcpyDeviceToDevice,
+                        static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
+  if (!g) return fail(PD_EINVAL, "null grid");
+  switch (option) {
+    case PD_OPT_ALLOW_UNSTABLE: g->allow_unstable = value ? 1 : 0; return PD_OK;
+    case PD_OPT_ROWS_PER_LANE:
+      if (value != 0 && !burst_rows_supported((int)value)) return fail(PD_EINVAL, "unsupported rows per lane");
+      g->opt_R = (int)value;
+      break;
+    case PD_OPT_PATCHES_PER_BLOCK:
+      if (value < 0 || value > 256) return fail(PD_EINVAL, "patches per block out of range");
+      g->opt_ppb = (int)value;
+      break;
+    default: return fail(PD_EINVAL, "unknown option");
+  }
+  choose_shape(g);
+  if (!g->R) {
+    g->opt_R = 0;
+    g->opt_ppb = 0;
+    choose_shape(g);
+    return fail(PD_EINVAL, "no launch shape with these options; reverted to automatic");
+  }
+  return PD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Internal declarations shared by the host API (pd_host.hip) and the kernels
+// (pd_coeff.hip, pd_burst.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/pd.h"
+
+namespace pdk {
+
+// Grid constants as the kernels see them (copied by value into kernel arguments).
+struct Geo {
+  int geometry;
+  double gparam;
+  double xi0, xi1, eta0, eta1;
+  int n_xi, n_eta, periodic;
+  double h_xi, h_eta;
+  int m_xi, m_eta;
+  int conv, c0mode;
+  double Dxi, Deta;     // macro spacings
+  double dxi, deta;     // micro spacings h/(m-1)
+  double kap_xi, kap_eta;
+  int P, npx, i_first, M;
+};
+
+// Offsets (in doubles) of the pieces of the stencil table: the same layout that
+// pd_get_tables documents.
+struct TabOff {
+  int s_xi, s_eta, L_xe, L_ee, ew, c_xi, c_eta, scal, size;
+};
+
+__host__ __device__ inline TabOff tab_off(int mx, int me) {
+  TabOff t;
+  t.s_xi = 0;
+  t.s_eta = mx;
+  t.L_xe = mx + me;           // [m_eta][3]: interpolation along eta at the xi edges
+  t.L_ee = t.L_xe + 3 * me;   // [m_xi][3]:  interpolation along xi at the eta edges
+  t.ew = t.L_ee + 3 * mx;     // xi-, xi+, eta-, eta+ (3 each)
+  t.c_xi = t.ew + 12;
+  t.c_eta = t.c_xi + mx;
+  t.scal = t.c_eta + me;      // Dxi, Deta, dxi, deta, r_xi, r_eta, kappa_xi, kappa_eta
+  t.size = t.scal + 8;
+  return t;
+}
+
+// Device-side clock of pd_solve: macro step n at time t0 + n dt; the fused kernels
+// read the macro field from buf[n & 1] and write buf[(n + 1) & 1].
+struct Clock {
+  double t0, dt;
+  long long n;
+  double* buf[2];
+};
+
+// Time factors and the constant part of the source, packed for kernel arguments.
+struct SrcInfo {
+  int ns;                 // time-dependent terms (<= 2)
+  int plane_t[2];         // their coefficient planes
+  int ttype[2];
+  double ta[2], tb[2], tc[2];
+  int nconst;             // constant terms folded into the static forcing
+  int plane_c[PD_MAXTERM];
+  double ca[PD_MAXTERM];
+};
+
+enum { MODE_SPLIT = 0, MODE_FUSED = 1 };
+
+struct BurstArgs {
+  Geo g;
+  SrcInfo src;
+  const double* coef;     // planes [5 + n_src][P][m_eta][m_xi]
+  const int* pmap;        // [P][11]
+  const double* tab;      // stencil tables
+  long long plane;        // P * m_xi * m_eta
+  // split mode
+  double* state;          // [P][m_eta][m_xi] in/out
+  const double* edge;     // [P][4][M]
+  // fused mode
+  const double* U;        // U_n
+  double* Unew;           // U_{n+1} (patch nodes)
+  const Clock* clk;       // non-null: take t_n and the buffers from the device clock
+  double t_n, dt, dt_macro, tau;
+  int n_t;
+  int ppb;                // patches per block
+  int* flag;              // non-finite flag
+};
+
+// Launchers implemented in the kernel translation units.
+hipError_t launch_coefficients(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
+                               double* coef, hipStream_t s);
+hipError_t launch_limits(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
+                         const double* coef, double* partial, int nblocks, double* out,
+                         hipStream_t s);
+hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
+                           Clock* clk, int advance_clock, hipStream_t s);
+hipError_t launch_initial(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
+                          hipStream_t s);
+hipError_t launch_clock_init(Clock* clk, double t0, double dt, double* b0, double* b1,
+                             hipStream_t s);
+hipError_t launch_lift_bc(const Geo& g, const int* pmap, const double* tab, const double* U,
+                          double* state, double* edge, hipStream_t s);
+hipError_t launch_restrict(const Geo& g, const double* state, double* Ubar, hipStream_t s);
+hipError_t launch_macro_update(const Geo& g, const int* pmap, const double* U,
+                               const double* Ubar, double* Unew, double dt_macro, double tau,
+                               int* flag, hipStream_t s);
+// Burst kernels: precision PD_F64/PD_F32, rows per lane R, mode split/fused.
+hipError_t launch_burst(int precision, int R, int mode, const BurstArgs& a, int blocks,
+                        int threads, size_t lds, hipStream_t s);
+bool burst_rows_supported(int R);
+
+// Dynamic LDS bytes of a burst launch.
+inline size_t burst_lds_bytes(int precision, int ppb, int mx, int me, int ns) {
+  size_t rs = precision == PD_F32 ? 4 : 8;
+  size_t tile = 2ull * ppb * (size_t)(mx + 2) * (me + 2) * rs;
+  tile = (tile + 15) & ~size_t(15);
+  const int TCH = 256;
+  return tile + (size_t)(ns > 0 ? ns : 1) * TCH * 8 + (size_t)ppb * me * 8 + 64;
+}
+
+}  // namespace pdk

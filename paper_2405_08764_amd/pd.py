@@ -1,0 +1,339 @@
+"""Thin ctypes binding of libpd.so (include/pd.h) with the same call names.
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch provides device memory and streams.  Loading fails loudly when the library has not
+been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpd.so")
+
+MAXMODE, MAXPOLAR, MAXTERM = 16, 4, 4
+GEOM = {"identity": 0, "sine": 1, "tanh": 2, "annulus": 3}
+CONV = {"upwind": 0, "central": 1}
+C0MODE = {"trapezoid": 0, "printed": 1}
+PREC = {"f64": 0, "f32": 1}
+FN = {"sin": 0, "cos": 1, "exp": 2, "poly": 3}
+TF = {"const": 0, "exp": 1, "sin": 2}
+OPT_ALLOW_UNSTABLE, OPT_ROWS_PER_LANE, OPT_PATCHES_PER_BLOCK = 1, 2, 3
+
+STATUS = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ESTATE", -3: "PD_EUNSTABLE", -4: "PD_EDEVICE",
+          -5: "PD_ENONFINITE", -6: "PD_ENOMEM"}
+
+
+class PdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("geometry", C.c_int32), ("gparam", C.c_double), ("xi0", C.c_double),
+                ("xi1", C.c_double), ("eta0", C.c_double), ("eta1", C.c_double),
+                ("n_xi", C.c_int32), ("n_eta", C.c_int32), ("periodic_xi", C.c_int32),
+                ("h_xi", C.c_double), ("h_eta", C.c_double), ("m_xi", C.c_int32),
+                ("m_eta", C.c_int32), ("conv", C.c_int32), ("c0mode", C.c_int32),
+                ("precision", C.c_int32), ("device", C.c_int32)]
+
+
+class Field(C.Structure):
+    _fields_ = [("c0", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("nmode", C.c_int32), ("amp", C.c_double * MAXMODE),
+                ("kx", C.c_double * MAXMODE), ("ky", C.c_double * MAXMODE),
+                ("ph", C.c_double * MAXMODE), ("npolar", C.c_int32),
+                ("pamp", C.c_double * MAXPOLAR), ("pc0", C.c_double * MAXPOLAR),
+                ("pc1", C.c_double * MAXPOLAR), ("pc2", C.c_double * MAXPOLAR),
+                ("pn", C.c_double * MAXPOLAR), ("pph", C.c_double * MAXPOLAR)]
+
+
+class Fn1(C.Structure):
+    _fields_ = [("type", C.c_int32), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double),
+                ("d", C.c_double)]
+
+
+class Sfun(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("amp", C.c_double), ("f", Fn1), ("g", Fn1)]
+
+
+class Tfun(C.Structure):
+    _fields_ = [("type", C.c_int32), ("a", C.c_double), ("b", C.c_double), ("c", C.c_double)]
+
+
+class CoeffDesc(C.Structure):
+    _fields_ = [("D11", Field), ("D22", Field), ("v1", Field), ("v2", Field), ("f", Field),
+                ("n_bc", C.c_int32), ("bc_t", Tfun * MAXTERM), ("bc_s", Sfun * MAXTERM),
+                ("n_src", C.c_int32), ("src_t", Tfun * MAXTERM),
+                ("src_c", C.c_double * MAXTERM), ("src_s", Sfun * MAXTERM)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_patches", C.c_int32), ("m_xi", C.c_int32), ("m_eta", C.c_int32),
+                ("n_xi", C.c_int32), ("n_eta", C.c_int32), ("n_points", C.c_int64),
+                ("workspace_bytes", C.c_size_t), ("dt_micro_limit", C.c_double),
+                ("dt_macro_limit", C.c_double), ("coefficients_set", C.c_int32),
+                ("n_time_sources", C.c_int32), ("rows_per_lane", C.c_int32),
+                ("patches_per_block", C.c_int32), ("block_threads", C.c_int32)]
+
+
+EXPORTS = {
+    "pd_create_grid": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(C.c_void_p)]),
+    "pd_destroy_grid": (C.c_int32, [C.c_void_p]),
+    "pd_query": (C.c_int32, [C.c_void_p, C.POINTER(Info)]),
+    "pd_bind_workspace": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "pd_set_coefficients": (C.c_int32, [C.c_void_p, C.POINTER(CoeffDesc), C.c_void_p]),
+    "pd_initial": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "pd_lift_bc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_micro_burst": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                   C.c_int32, C.c_void_p]),
+    "pd_restrict": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_macro_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                  C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
+    "pd_patch_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                  C.c_double, C.c_int32, C.c_void_p]),
+    "pd_apply_boundary": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "pd_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
+                             C.c_double, C.c_int32, C.c_void_p]),
+    "pd_sync": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pd_get_patch_map": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pd_get_tables_size": (C.c_int32, [C.c_void_p]),
+    "pd_get_tables": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pd_copy_coefficients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_set_option": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64]),
+    "pd_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpd.so; raises if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2405_08764_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise PdError(status, lib().pd_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None and not torch.cuda.is_available():
+        return C.c_void_p(0)
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _field(d):
+    F = Field()
+    F.c0, F.cx, F.cy = d["c0"], d["cx"], d["cy"]
+    F.nmode = len(d["modes"])
+    for k, (a, kx, ky, ph) in enumerate(d["modes"]):
+        F.amp[k], F.kx[k], F.ky[k], F.ph[k] = a, kx, ky, ph
+    F.npolar = len(d["polar"])
+    for k, (a, p0, p1, p2, n, ph) in enumerate(d["polar"]):
+        F.pamp[k], F.pc0[k], F.pc1[k], F.pc2[k], F.pn[k], F.pph[k] = a, p0, p1, p2, n, ph
+    return F
+
+
+def _fn1(t):
+    f = Fn1()
+    f.type = FN[t[0]]
+    v = list(t[1:]) + [0.0] * (4 - len(t) + 1)
+    f.a, f.b, f.c, f.d = v[:4]
+    return f
+
+
+def _sfun(s):
+    S = Sfun()
+    S.kind = 0 if s[0] == "cart" else 1
+    S.amp = s[1]
+    S.f, S.g = _fn1(s[2]), _fn1(s[3])
+    return S
+
+
+def _tfun(t):
+    T = Tfun()
+    T.type = TF[t[0]]
+    v = list(t[1:]) + [0.0] * (3 - len(t) + 1)
+    T.a, T.b, T.c = v[:3]
+    return T
+
+
+def grid_desc(g, precision="f64", device=0):
+    D = GridDesc()
+    D.geometry = GEOM[g["geometry"]]
+    D.gparam = g["gparam"]
+    D.xi0, D.xi1, D.eta0, D.eta1 = g["xi0"], g["xi1"], g["eta0"], g["eta1"]
+    D.n_xi, D.n_eta = g["n_xi"], g["n_eta"]
+    D.periodic_xi = int(g["periodic_xi"])
+    D.h_xi, D.h_eta = g["h_xi"], g["h_eta"]
+    D.m_xi, D.m_eta = g["m_xi"], g["m_eta"]
+    D.conv = CONV[g["conv"]]
+    D.c0mode = C0MODE[g["c0"]]
+    D.precision = PREC[precision]
+    D.device = device
+    return D
+
+
+def coeff_desc(prob):
+    Cd = CoeffDesc()
+    fl = prob["fields"]
+    Cd.D11, Cd.D22, Cd.v1, Cd.v2, Cd.f = (_field(fl[k]) for k in ("D11", "D22", "v1", "v2", "f"))
+    Cd.n_bc = len(prob["bc"])
+    for m, (t, s) in enumerate(prob["bc"]):
+        Cd.bc_t[m], Cd.bc_s[m] = _tfun(t), _sfun(s)
+    Cd.n_src = len(prob["src"])
+    for k, (t, c, s) in enumerate(prob["src"]):
+        Cd.src_t[k], Cd.src_c[k], Cd.src_s[k] = _tfun(t), c, _sfun(s)
+    return Cd
+
+
+class Grid:
+    """One problem on one device: grid, workspace (a torch uint8 tensor) and coefficients.
+
+    Method names follow the C ABI (pd_lift_bc -> lift_bc, ...).  Tensors are float64 on
+    the grid's device; calls run on the current torch stream.
+    """
+
+    def __init__(self, prob, precision="f64", device=0, coefficients=True):
+        self.prob = prob
+        self.L = lib()
+        self.device = torch.device("cuda", device) if torch.cuda.is_available() else None
+        self.h = C.c_void_p()
+        _check(self.L.pd_create_grid(C.byref(grid_desc(prob["grid"], precision, device)),
+                                     C.byref(self.h)))
+        self.info = self.query()
+        self.P = self.info.n_patches
+        self.mx, self.me = self.info.m_xi, self.info.m_eta
+        self.nx, self.ne = self.info.n_xi, self.info.n_eta
+        self.M = max(self.mx, self.me)
+        self.ws = None
+        if coefficients:
+            self.bind()
+            self.set_coefficients()
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            self.L.pd_destroy_grid(self.h)
+            self.h = C.c_void_p()
+
+    def query(self):
+        I = Info()
+        _check(self.L.pd_query(self.h, C.byref(I)))
+        return I
+
+    def bind(self):
+        n = self.info.workspace_bytes
+        self.ws = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        _check(self.L.pd_bind_workspace(self.h, C.c_void_p(aligned), n))
+
+    def set_coefficients(self, prob=None, stream=None):
+        self._cd = coeff_desc(prob or self.prob)
+        _check(self.L.pd_set_coefficients(self.h, C.byref(self._cd), _stream(stream)))
+        self.info = self.query()
+
+    def set_option(self, option, value):
+        _check(self.L.pd_set_option(self.h, option, int(value)))
+        self.info = self.query()
+
+    # -- host-side tables
+    def patch_map(self):
+        out = torch.zeros((self.P, 11), dtype=torch.int32)
+        _check(self.L.pd_get_patch_map(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def tables(self):
+        out = torch.zeros(self.L.pd_get_tables_size(self.h), dtype=torch.float64)
+        _check(self.L.pd_get_tables(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def coefficients(self):
+        nc = 5 + len(self.prob["src"])
+        out = torch.empty((nc, self.P, self.me, self.mx), dtype=torch.float64, device=self.device)
+        _check(self.L.pd_copy_coefficients(self.h, _ptr(out), _stream()))
+        return out
+
+    # -- the steps
+    def new_U(self):
+        return torch.zeros((self.ne, self.nx), dtype=torch.float64, device=self.device)
+
+    def initial(self, t=None, U=None):
+        U = self.new_U() if U is None else U
+        t = self.prob["time"]["t0"] if t is None else t
+        _check(self.L.pd_initial(self.h, _ptr(U), float(t), _stream()))
+        return U
+
+    def lift_bc(self, U):
+        state = torch.empty((self.P, self.me, self.mx), dtype=torch.float64, device=self.device)
+        edge = torch.empty((self.P, 4, self.M), dtype=torch.float64, device=self.device)
+        _check(self.L.pd_lift_bc(self.h, _ptr(U), _ptr(state), _ptr(edge), _stream()))
+        return state, edge
+
+    def micro_burst(self, state, edge, t_n, dt, n_t):
+        _check(self.L.pd_micro_burst(self.h, _ptr(state), _ptr(edge), float(t_n), float(dt),
+                                     int(n_t), _stream()))
+        return state
+
+    def restrict(self, state):
+        Ub = torch.empty(self.P, dtype=torch.float64, device=self.device)
+        _check(self.L.pd_restrict(self.h, _ptr(state), _ptr(Ub), _stream()))
+        return Ub
+
+    def macro_step(self, U_n, t_n, dt_macro=None, dt_micro=None, n_t=None, Ubar=None,
+                   out=None):
+        t = self.prob["time"]
+        dt_macro = t["dt_macro"] if dt_macro is None else dt_macro
+        dt_micro = t["dt_micro"] if dt_micro is None else dt_micro
+        n_t = t["n_t"] if n_t is None else n_t
+        out = self.new_U() if out is None else out
+        _check(self.L.pd_macro_step(self.h, _ptr(U_n), _ptr(out), float(t_n), float(dt_macro),
+                                    float(dt_micro), int(n_t), _ptr(Ubar), _stream()))
+        return out
+
+    def patch_step(self, U_n, t_n, out, dt_macro=None, dt_micro=None, n_t=None):
+        t = self.prob["time"]
+        _check(self.L.pd_patch_step(
+            self.h, _ptr(U_n), _ptr(out), float(t_n),
+            float(t["dt_macro"] if dt_macro is None else dt_macro),
+            float(t["dt_micro"] if dt_micro is None else dt_micro),
+            int(t["n_t"] if n_t is None else n_t), _stream()))
+        return out
+
+    def apply_boundary(self, U, t):
+        _check(self.L.pd_apply_boundary(self.h, _ptr(U), float(t), _stream()))
+        return U
+
+    def solve(self, U=None, n_steps=None, t0=None, dt_macro=None, dt_micro=None, n_t=None):
+        t = self.prob["time"]
+        U = self.initial() if U is None else U
+        _check(self.L.pd_solve(self.h, _ptr(U), float(t["t0"] if t0 is None else t0),
+                               float(t["dt_macro"] if dt_macro is None else dt_macro),
+                               int(t["n_steps"] if n_steps is None else n_steps),
+                               float(t["dt_micro"] if dt_micro is None else dt_micro),
+                               int(t["n_t"] if n_t is None else n_t), _stream()))
+        return U
+
+    def sync(self):
+        _check(self.L.pd_sync(self.h, _stream()))

@@ -543,3 +543,21 @@ def test_tau_insensitivity_sec42(oracle_mod):
     ref = out[1]
     for U in out:
         assert np.max(np.abs(U - ref)) / np.max(np.abs(ref)) < 5e-3
+
+
+@pytest.mark.parametrize("name", ["config1", "config2_small", "config3_small"])
+def test_roundoff_floor_of_the_fp64_oracle(oracle_mod, name):
+    """The FP64 oracle against the same source built in x87 extended precision: the
+    difference is the FP64 build's own round-off, which must sit far below the 1e-11
+    parity bar for the configured ratio dt_macro / tau = 20 (the printed cases with
+    tau = 1e-6 amplify round-off by dt_macro / tau = 400-500; the parity tests compare
+    against the extended build for that reason)."""
+    prob = {"config1": W.config1(),
+            "config2_small": W.config2(n=17, m=17, n_steps=12),
+            "config3_small": W.config3(n_r=11, n_theta=16, m=21, n_steps=8)}[name]
+    prob = _fit_n_t(oracle_mod, prob)
+    a = make(oracle_mod, prob, threads=4).solve()
+    b = oracle_mod.Oracle(prob, threads=4, extended=True).solve()
+    m = make(oracle_mod, prob).patch_mask()
+    floor = np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m])
+    assert 0.0 < floor < 1e-12, floor

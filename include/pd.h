@@ -128,6 +128,8 @@ typedef struct {
   int32_t coefficients_set;
   int32_t n_time_sources;    /* source terms with a non-constant time factor           */
   int32_t rows_per_lane, patches_per_block, block_threads; /* current launch shape     */
+  int32_t cols_per_lane;
+  int32_t exchange;          /* 1: neighbours through LDS, 2: inside one wave (DPP)   */
 } pd_info;
 
 typedef struct pd_grid_s* pd_grid;
@@ -157,8 +159,8 @@ pd_status pd_initial(pd_grid g, double* U, double t, void* stream);
 pd_status pd_lift_bc(pd_grid g, const double* U, double* patch_state, double* edge,
                      void* stream);
 /* Step (iii): n_t explicit forward-Euler nano steps of size dt_micro from time t_n inside
- * every patch with the edge gradients held fixed (tau = n_t dt_micro).  patch_state is
- * updated in place.  PD_EUNSTABLE if dt_micro exceeds the explicit bound. */
+ * every patch with the edge gradients held fixed (tau = n_t dt_micro, 1 <= n_t <= 65536).
+ * patch_state is updated in place.  PD_EUNSTABLE if dt_micro exceeds the explicit bound. */
 pd_status pd_micro_burst(pd_grid g, double* patch_state, const double* edge, double t_n,
                          double dt_micro, int32_t n_t, void* stream);
 /* Step (iv): eq. (Restriction) by the composite trapezoidal rule, Ubar[P]. */
@@ -199,11 +201,16 @@ pd_status pd_get_tables(pd_grid g, double* host_out);
  * omega, phi, then each source term's spatial part in descriptor order). */
 pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
 
-/* Options: PD_OPT_ALLOW_UNSTABLE (0/1) skips the stability guard; PD_OPT_ROWS_PER_LANE
- * and PD_OPT_PATCHES_PER_BLOCK set the burst launch shape (0 = automatic). */
+/* Options: PD_OPT_ALLOW_UNSTABLE (0/1) skips the stability guard; PD_OPT_ROWS_PER_LANE,
+ * PD_OPT_COLS_PER_LANE (1..3), PD_OPT_PATCHES_PER_BLOCK, PD_OPT_BLOCK_THREADS (upper bound,
+ * 64..256) and PD_OPT_EXCHANGE (1 LDS, 2 in-wave) set the fused burst's launch shape
+ * (0 = automatic).  Results do not depend on the launch shape (bitwise). */
 #define PD_OPT_ALLOW_UNSTABLE 1
 #define PD_OPT_ROWS_PER_LANE 2
 #define PD_OPT_PATCHES_PER_BLOCK 3
+#define PD_OPT_BLOCK_THREADS 4
+#define PD_OPT_COLS_PER_LANE 5
+#define PD_OPT_EXCHANGE 6
 pd_status pd_set_option(pd_grid g, int32_t option, int64_t value);
 
 const char* pd_last_error(void);

@@ -14,19 +14,30 @@
 #include "pd_internal.h"
 
 namespace pdk {
-hipError_t launch_burst_f64(int R, int mode, const BurstArgs& a, int blocks, int threads,
-                            size_t lds, hipStream_t s);
-hipError_t launch_burst_f32(int R, int mode, const BurstArgs& a, int blocks, int threads,
-                            size_t lds, hipStream_t s);
+#define PD_DECL(tag)                                                                      \
+  hipError_t launch_burst_##tag(int R, int C, int mode, const BurstArgs& a, int blocks,   \
+                                int threads, size_t lds, hipStream_t s);
+PD_DECL(lds_f64)
+PD_DECL(lds_f32)
+PD_DECL(x_f64)
+PD_DECL(x_f32)
+#undef PD_DECL
 
-hipError_t launch_burst(int precision, int R, int mode, const BurstArgs& a, int blocks,
-                        int threads, size_t lds, hipStream_t s) {
-  return precision == PD_F32 ? launch_burst_f32(R, mode, a, blocks, threads, lds, s)
-                             : launch_burst_f64(R, mode, a, blocks, threads, lds, s);
+hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const BurstArgs& a,
+                        int blocks, int threads, size_t lds, hipStream_t s) {
+  if (mode == MODE_SPLIT) xch = XCH_LDS;  // the in-wave kernels are fused-only
+  if (xch == XCH_LANES)
+    return precision == PD_F32 ? launch_burst_x_f32(R, C, mode, a, blocks, threads, lds, s)
+                               : launch_burst_x_f64(R, C, mode, a, blocks, threads, lds, s);
+  return precision == PD_F32 ? launch_burst_lds_f32(R, C, mode, a, blocks, threads, lds, s)
+                             : launch_burst_lds_f64(R, C, mode, a, blocks, threads, lds, s);
 }
 
-bool burst_rows_supported(int R) {
-  return R == 3 || R == 4 || R == 5 || R == 6 || R == 7 || R == 8 || R == 9 || R == 11;
+bool burst_shape_supported(int R, int C) {
+  if (C == 1) return R == 3 || R == 4 || R == 5 || R == 6 || R == 7 || R == 8 || R == 9 || R == 11;
+  if (C == 2) return R >= 2 && R <= 6;
+  if (C == 3) return R == 2 || R == 3;
+  return false;
 }
 }  // namespace pdk
 
@@ -93,7 +104,7 @@ struct pd_grid_s {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_coef = 0, off_pmap = 0, off_tab = 0, off_desc = 0, off_V = 0, off_flag = 0,
-         off_clock = 0, off_part = 0, off_lim = 0, need = 0;
+         off_clock = 0, off_part = 0, off_lim = 0, off_ttab = 0, need = 0;
   // coefficients
   bool coeffs_set = false;
   pd_coeff_desc cd{};
@@ -101,9 +112,12 @@ struct pd_grid_s {
   SrcInfo src{};
   double lim_micro = 0.0, lim_macro = 0.0;
   // options
-  int allow_unstable = 0, opt_R = 0, opt_ppb = 0;
+  int allow_unstable = 0, opt_R = 0, opt_C = 0, opt_ppb = 0, opt_threads = 0, opt_xch = 0;
   // launch shape
-  int R = 0, ppb = 0, threads = 0, blocks = 0;
+  int R = 0, C = 0, xch = 0, ppb = 0, threads = 0, blocks = 0;
+  // split-mode launch shape (always the LDS-exchange kernel)
+  int sR = 0, sC = 0, sppb = 0, sthreads = 0, sblocks = 0;
+  size_t slds = 0;
   size_t lds = 0;
   // graph replay of pd_solve
   hipStream_t cap = nullptr;
@@ -114,7 +128,7 @@ struct pd_grid_s {
   double g_dtm = 0, g_dt = 0;
   int g_nt = 0;
   double* g_U = nullptr;
-  int g_R = 0, g_ppb = 0;
+  int g_R = 0, g_C = 0, g_ppb = 0, g_threads = 0, g_xch = 0;
 
   double* coef() { return reinterpret_cast<double*>(ws + off_coef); }
   int* dpmap() { return reinterpret_cast<int*>(ws + off_pmap); }
@@ -125,6 +139,7 @@ struct pd_grid_s {
   Clock* clock() { return reinterpret_cast<Clock*>(ws + off_clock); }
   double* part() { return reinterpret_cast<double*>(ws + off_part); }
   double* lim() { return reinterpret_cast<double*>(ws + off_lim); }
+  double* ttab() { return reinterpret_cast<double*>(ws + off_ttab); }
 };
 
 namespace {
@@ -137,36 +152,80 @@ void drop_graph(pd_grid g) {
   g->g_steps = 0;
 }
 
-// Launch shape of the burst: R rows per lane, ppb patches per 256-thread block, chosen for
-// the fewest idle lanes and padding rows (both are wasted VALU slots).
-void choose_shape(pd_grid g) {
+// Launch shape of the burst: C columns x R rows per lane, ppb patches per block, and the
+// neighbour exchange.  Candidates are ranked by the useful fraction of the lane slots
+// (idle lanes and padding points are wasted VALU issue); on ties, the in-wave exchange
+// (no LDS traffic in the nano-step loop), then wider lane blocks (fewer exchanged values
+// per point), then smaller blocks.  pd_autotune replaces this guess by measurement.
+struct Shape {
+  int R, C, xch, ppb, threads;
+  double score;
+};
+
+bool next_shape(pd_grid g, int xch_only, bool split, std::vector<Shape>& out) {
   const int mx = g->g.m_xi, me = g->g.m_eta;
-  int bestR = 0, bestP = 0;
-  double best = -1.0;
-  const int cand[] = {3, 4, 5, 6, 7, 8, 9, 11};
-  for (int R : cand) {
-    if (g->opt_R && R != g->opt_R) continue;
-    const int B = (me + R - 1) / R;
-    const int LP = mx * B;
-    if (LP > 256) continue;
-    int ppb = 256 / LP;
-    if (g->opt_ppb) ppb = g->opt_ppb < ppb ? g->opt_ppb : ppb;
-    const int threads = ((ppb * LP + 63) / 64) * 64;
-    if (burst_lds_bytes(g->d.precision, ppb, mx, me, g->src.ns) > 65536) continue;
-    const double eff = (double)ppb * mx * me / ((double)threads * R);
-    if (eff > best + 1e-9) {
-      best = eff;
-      bestR = R;
-      bestP = ppb;
+  const int candR[] = {2, 3, 4, 5, 6, 7, 8, 9, 11};
+  out.clear();
+  for (int xch = XCH_LDS; xch <= XCH_LANES; ++xch) {
+    if (split && xch != XCH_LDS) continue;
+    if (xch_only && xch != xch_only) continue;
+    for (int C = 1; C <= 3; ++C) {
+      if (g->opt_C && C != g->opt_C) continue;
+      for (int R : candR) {
+        if (!burst_shape_supported(R, C) || (g->opt_R && R != g->opt_R)) continue;
+        const int Lb = (mx + C - 1) / C, B = (me + R - 1) / R;
+        const int LP = Lb * B;
+        for (int cap = 64; cap <= 256; cap += 64) {
+          if (xch == XCH_LANES && cap != 64) break;
+          if (g->opt_threads && cap > g->opt_threads) break;
+          if (LP > cap) continue;
+          int ppb = cap / LP;
+          if (g->opt_ppb) ppb = g->opt_ppb < ppb ? g->opt_ppb : ppb;
+          const int threads = ((ppb * LP + 63) / 64) * 64;
+          if (burst_lds_bytes(g->d.precision, R, C, xch, threads, ppb, mx, me, g->src.ns) > 65536)
+            continue;
+          const double eff = (double)ppb * mx * me / ((double)threads * R * C);
+          const double score = eff + 2e-3 * (xch == XCH_LANES) + 1e-3 * (C - 1) - 1e-5 * threads;
+          out.push_back({R, C, xch, ppb, threads, score});
+        }
+      }
     }
   }
-  g->R = bestR;
-  g->ppb = bestP;
-  if (bestR) {
-    const int LP = mx * ((me + bestR - 1) / bestR);
-    g->threads = ((bestP * LP + 63) / 64) * 64;
-    g->blocks = (g->g.P + bestP - 1) / bestP;
-    g->lds = burst_lds_bytes(g->d.precision, bestP, mx, me, g->src.ns);
+  return !out.empty();
+}
+
+void apply_shape(pd_grid g, const Shape& b) {
+  g->R = b.R;
+  g->C = b.C;
+  g->xch = b.xch;
+  g->ppb = b.ppb;
+  g->threads = b.threads;
+  g->blocks = (g->g.P + b.ppb - 1) / b.ppb;
+  g->lds = burst_lds_bytes(g->d.precision, b.R, b.C, b.xch, b.threads, b.ppb, g->g.m_xi,
+                           g->g.m_eta, g->src.ns);
+}
+
+void choose_shape(pd_grid g) {
+  std::vector<Shape> c;
+  g->R = 0;
+  g->sR = 0;
+  if (next_shape(g, g->opt_xch, false, c)) {
+    const Shape* b = &c[0];
+    for (const Shape& x : c)
+      if (x.score > b->score) b = &x;
+    apply_shape(g, *b);
+  }
+  if (next_shape(g, XCH_LDS, true, c)) {
+    const Shape* b = &c[0];
+    for (const Shape& x : c)
+      if (x.score > b->score) b = &x;
+    g->sR = b->R;
+    g->sC = b->C;
+    g->sppb = b->ppb;
+    g->sthreads = b->threads;
+    g->sblocks = (g->g.P + b->ppb - 1) / b->ppb;
+    g->slds = burst_lds_bytes(g->d.precision, b->R, b->C, XCH_LDS, b->threads, b->ppb,
+                              g->g.m_xi, g->g.m_eta, g->src.ns);
   }
 }
 
@@ -206,12 +265,13 @@ pd_status need_coeffs(pd_grid g) {
   pd_status s = need_ws(g);
   if (s) return s;
   if (!g->coeffs_set) return fail(PD_ESTATE, "coefficients not set");
-  if (!g->R) return fail(PD_EINVAL, "no supported burst launch shape for this patch size");
+  if (!g->R || !g->sR) return fail(PD_EINVAL, "no supported burst launch shape for this patch size");
   return PD_OK;
 }
 
 pd_status guard_micro(pd_grid g, double dt, int n_t) {
   if (!(dt > 0.0) || n_t < 1) return fail(PD_EINVAL, "dt_micro must be > 0 and n_t >= 1");
+  if (n_t > MAX_NT) return fail(PD_EINVAL, "n_t above the supported 65536 nano steps per burst");
   if (!g->allow_unstable && dt > g->lim_micro * (1.0 + 1e-12)) {
     char b[160];
     snprintf(b, sizeof b, "dt_micro %.6g above the explicit bound %.6g", dt, g->lim_micro);
@@ -245,6 +305,7 @@ BurstArgs base_args(pd_grid g, double t_n, double dt, int n_t) {
   a.n_t = n_t;
   a.ppb = g->ppb;
   a.flag = g->flag();
+  a.ttab = g->ttab();
   return a;
 }
 
@@ -359,6 +420,7 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
   g->off_clock = o; o = align256(o + sizeof(Clock));
   g->off_part = o; o = align256(o + 2 * NB_LIM * sizeof(double));
   g->off_lim = o; o = align256(o + 2 * sizeof(double));
+  g->off_ttab = o; o = align256(o + 2 * (size_t)MAX_NT * sizeof(double));
   g->need = o;
   choose_shape(g);
   *out = g;
@@ -392,6 +454,8 @@ pd_status pd_query(pd_grid g, pd_info* out) {
   I.coefficients_set = g->coeffs_set ? 1 : 0;
   I.n_time_sources = g->src.ns;
   I.rows_per_lane = g->R;
+  I.cols_per_lane = g->C;
+  I.exchange = g->xch;
   I.patches_per_block = g->ppb;
   I.block_threads = g->threads;
   return PD_OK;
@@ -494,8 +558,11 @@ pd_status pd_micro_burst(pd_grid g, double* state, const double* edge, double t_
   BurstArgs a = base_args(g, t_n, dt, n_t);
   a.state = state;
   a.edge = edge;
-  HIPCHK(launch_burst(g->d.precision, g->R, MODE_SPLIT, a, g->blocks, g->threads, g->lds,
-                      static_cast<hipStream_t>(stream)));
+  a.ppb = g->sppb;
+  HIPCHK(launch_time_table(g->src, nullptr, t_n, dt, n_t, g->ttab(),
+                           static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_burst(g->d.precision, g->sR, g->sC, XCH_LDS, MODE_SPLIT, a, g->sblocks,
+                      g->sthreads, g->slds, static_cast<hipStream_t>(stream)));
   return PD_OK;
 }
 
@@ -527,7 +594,8 @@ pd_status pd_macro_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
     a.Unew = U_np1;
     a.dt_macro = dt_macro;
     a.tau = tau;
-    HIPCHK(launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads, g->lds, s));
+    HIPCHK(launch_time_table(g->src, nullptr, t_n, dt, n_t, g->ttab(), s));
+    HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds, s));
   }
   HIPCHK(launch_boundary(g->g, g->ddesc(), U_np1, t_n + dt_macro, nullptr, 0, s));
   return PD_OK;
@@ -545,7 +613,9 @@ pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
   a.Unew = U_np1;
   a.dt_macro = dt_macro;
   a.tau = n_t * dt;
-  HIPCHK(launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads, g->lds,
+  HIPCHK(launch_time_table(g->src, nullptr, t_n, dt, n_t, g->ttab(),
+                           static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds,
                       static_cast<hipStream_t>(stream)));
   return PD_OK;
 }
@@ -582,7 +652,8 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
   a.clk = g->clock();
   const int S = n_steps < 16 ? n_steps : 16;  // macro steps per graph replay
   const bool reuse = g->gexec && g->g_steps == S && g->g_dtm == dt_macro && g->g_dt == dt &&
-                     g->g_nt == n_t && g->g_U == U && g->g_R == g->R && g->g_ppb == g->ppb;
+                     g->g_nt == n_t && g->g_U == U && g->g_R == g->R && g->g_C == g->C &&
+                     g->g_ppb == g->ppb && g->g_threads == g->threads && g->g_xch == g->xch;
   if (own) {
     HIPCHK(hipEventRecord(g->ev_in, s));
     HIPCHK(hipStreamWaitEvent(w, g->ev_in, 0));
@@ -592,8 +663,9 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     drop_graph(g);
     HIPCHK(hipStreamBeginCapture(w, hipStreamCaptureModeThreadLocal));
     for (int q = 0; q < S; ++q) {
-      hipError_t e1 = launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads,
-                                   g->lds, w);
+      hipError_t e0 = launch_time_table(g->src, g->clock(), t0, dt, n_t, g->ttab(), w);
+      hipError_t e1 = e0 != hipSuccess ? e0 : launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a,
+                                                           g->blocks, g->threads, g->lds, w);
       hipError_t e2 = launch_boundary(g->g, g->ddesc(), nullptr, 0.0, g->clock(), 1, w);
       if (e1 != hipSuccess || e2 != hipSuccess) {
         hipGraph_t junk = nullptr;
@@ -610,12 +682,16 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     g->g_nt = n_t;
     g->g_U = U;
     g->g_R = g->R;
+    g->g_C = g->C;
     g->g_ppb = g->ppb;
+    g->g_threads = g->threads;
+    g->g_xch = g->xch;
   }
   const int reps = n_steps / S, rem = n_steps - reps * S;
   for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(g->gexec, w));
   for (int q = 0; q < rem; ++q) {
-    HIPCHK(launch_burst(g->d.precision, g->R, MODE_FUSED, a, g->blocks, g->threads, g->lds, w));
+    HIPCHK(launch_time_table(g->src, g->clock(), t0, dt, n_t, g->ttab(), w));
+    HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds, w));
     HIPCHK(launch_boundary(g->g, g->ddesc(), nullptr, 0.0, g->clock(), 1, w));
   }
   if (n_steps & 1)
@@ -672,19 +748,35 @@ pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
   switch (option) {
     case PD_OPT_ALLOW_UNSTABLE: g->allow_unstable = value ? 1 : 0; return PD_OK;
     case PD_OPT_ROWS_PER_LANE:
-      if (value != 0 && !burst_rows_supported((int)value)) return fail(PD_EINVAL, "unsupported rows per lane");
+      if (value < 0 || value > 11) return fail(PD_EINVAL, "unsupported rows per lane");
       g->opt_R = (int)value;
+      break;
+    case PD_OPT_COLS_PER_LANE:
+      if (value < 0 || value > 3) return fail(PD_EINVAL, "columns per lane must be 1, 2 or 3");
+      g->opt_C = (int)value;
+      break;
+    case PD_OPT_EXCHANGE:
+      if (value < 0 || value > 2) return fail(PD_EINVAL, "exchange must be 0, 1 (LDS) or 2 (lanes)");
+      g->opt_xch = (int)value;
       break;
     case PD_OPT_PATCHES_PER_BLOCK:
       if (value < 0 || value > 256) return fail(PD_EINVAL, "patches per block out of range");
       g->opt_ppb = (int)value;
+      break;
+    case PD_OPT_BLOCK_THREADS:
+      if (value != 0 && (value < 64 || value > 256 || value % 64))
+        return fail(PD_EINVAL, "block threads must be 64, 128, 192 or 256");
+      g->opt_threads = (int)value;
       break;
     default: return fail(PD_EINVAL, "unknown option");
   }
   choose_shape(g);
   if (!g->R) {
     g->opt_R = 0;
+    g->opt_C = 0;
     g->opt_ppb = 0;
+    g->opt_threads = 0;
+    g->opt_xch = 0;
     choose_shape(g);
     return fail(PD_EINVAL, "no launch shape with these options; reverted to automatic");
   }

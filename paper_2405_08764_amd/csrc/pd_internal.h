@@ -65,6 +65,9 @@ struct SrcInfo {
 };
 
 enum { MODE_SPLIT = 0, MODE_FUSED = 1 };
+// Neighbour exchange of the burst: through LDS (any block size) or inside one wave
+// (DPP wave shifts and ds_bpermute, single-wave blocks).
+enum { XCH_LDS = 1, XCH_LANES = 2 };
 
 struct BurstArgs {
   Geo g;
@@ -80,6 +83,7 @@ struct BurstArgs {
   const double* U;        // U_n
   double* Unew;           // U_{n+1} (patch nodes)
   const Clock* clk;       // non-null: take t_n and the buffers from the device clock
+  const double* ttab;     // [ns][n_t] time factors T_j(t_n + s dt)
   double t_n, dt, dt_macro, tau;
   int n_t;
   int ppb;                // patches per block
@@ -104,18 +108,28 @@ hipError_t launch_restrict(const Geo& g, const double* state, double* Ubar, hipS
 hipError_t launch_macro_update(const Geo& g, const int* pmap, const double* U,
                                const double* Ubar, double* Unew, double dt_macro, double tau,
                                int* flag, hipStream_t s);
-// Burst kernels: precision PD_F64/PD_F32, rows per lane R, mode split/fused.
-hipError_t launch_burst(int precision, int R, int mode, const BurstArgs& a, int blocks,
-                        int threads, size_t lds, hipStream_t s);
-bool burst_rows_supported(int R);
+// Time factors of the time-dependent source terms for one burst.
+hipError_t launch_time_table(const SrcInfo& src, const Clock* clk, double t_n, double dt,
+                             int n_t, double* out, hipStream_t s);
+constexpr int MAX_NT = 65536;  // nano steps per burst (size of the time-factor table)
+// Burst kernels: precision PD_F64/PD_F32, C columns x R rows per lane, exchange, mode.
+hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const BurstArgs& a,
+                        int blocks, int threads, size_t lds, hipStream_t s);
+bool burst_shape_supported(int R, int C);
 
-// Dynamic LDS bytes of a burst launch.
-inline size_t burst_lds_bytes(int precision, int ppb, int mx, int me, int ns) {
-  size_t rs = precision == PD_F32 ? 4 : 8;
-  size_t tile = 2ull * ppb * (size_t)(mx + 2) * (me + 2) * rs;
-  tile = (tile + 15) & ~size_t(15);
+// Dynamic LDS bytes of a burst launch: the lane-major exchange tiles (double-buffered,
+// guard of lanes-per-band + 1 words on both sides) or the FP64 lifted tile of the
+// prologue, whichever is larger, then the time-factor chunk and the restriction rows.
+inline size_t burst_lds_bytes(int precision, int R, int C, int xch, int threads, int ppb,
+                              int mx, int me, int ns) {
+  const size_t rs = precision == PD_F32 ? 4 : 8;
+  const int Lb = (mx + C - 1) / C;
+  const size_t nbuf = xch == XCH_LANES ? 1 : 2;
+  const size_t exch = nbuf * R * C * (size_t)(threads + 2 * (Lb + 1)) * rs;
+  const size_t lift = (size_t)ppb * (mx + 2) * (me + 2) * 8;
+  const size_t region = ((exch > lift ? exch : lift) + 15) & ~size_t(15);
   const int TCH = 256;
-  return tile + (size_t)(ns > 0 ? ns : 1) * TCH * 8 + (size_t)ppb * me * 8 + 64;
+  return region + (size_t)(ns > 0 ? ns : 1) * TCH * 8 + (size_t)ppb * me * 8 + 64;
 }
 
 }  // namespace pdk

@@ -174,11 +174,14 @@ def test_solve_matches_oracle(pd, oracle_mod, problems, case, precision):
     assert err <= (1e-11 if precision == "f64" else 5e-6), err
 
 
+@pytest.mark.parametrize("xch", [1, 2])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_fused_step_equals_split_path(pd, oracle_mod, problems, precision):
-    """The fused kernel and the stage-by-stage calls compute the same macro step."""
+def test_fused_step_equals_split_path(pd, oracle_mod, problems, precision, xch):
+    """The fused kernel (either neighbour exchange) and the stage-by-stage calls compute
+    the same macro step."""
     prob = problems["config3_16x11"]
     g = pd.Grid(prob, precision=precision)
+    g.set_option(pd.OPT_EXCHANGE, xch)
     t = prob["time"]
     U = g.initial()
     fused = g.macro_step(U, 0.0)
@@ -242,15 +245,26 @@ def test_bitwise_determinism_across_runs_and_launch_shapes(pd, problems):
     ref = g.solve().cpu().numpy()
     again = g.solve().cpu().numpy()
     assert ref.tobytes() == again.tobytes()
-    for R in (3, 4, 5, 6, 7, 8, 9, 11):
-        for ppb in (1, 2, 0):
-            try:
-                g.set_option(pd.OPT_ROWS_PER_LANE, R)
-                g.set_option(pd.OPT_PATCHES_PER_BLOCK, ppb)
-            except pd.PdError:
-                continue
-            out = g.solve().cpu().numpy()
-            assert out.tobytes() == ref.tobytes(), (R, ppb)
+    seen = set()
+    for xch in (1, 2):
+        for C in (1, 2, 3):
+            for R in (2, 3, 4, 5, 6, 7, 8, 9, 11):
+                for ppb in (1, 2, 0):
+                    try:
+                        g.set_option(pd.OPT_EXCHANGE, xch)
+                        g.set_option(pd.OPT_COLS_PER_LANE, C)
+                        g.set_option(pd.OPT_ROWS_PER_LANE, R)
+                        g.set_option(pd.OPT_PATCHES_PER_BLOCK, ppb)
+                    except pd.PdError:
+                        continue
+                    I = g.query()
+                    key = (I.exchange, I.cols_per_lane, I.rows_per_lane, I.patches_per_block)
+                    if (I.exchange, I.cols_per_lane, I.rows_per_lane) != (xch, C, R) or key in seen:
+                        continue
+                    seen.add(key)
+                    out = g.solve().cpu().numpy()
+                    assert out.tobytes() == ref.tobytes(), key
+    assert {k[0] for k in seen} == {1, 2}, seen
 
 
 def test_graph_solve_equals_single_steps_and_resume(pd, problems):

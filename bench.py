@@ -18,6 +18,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6e12, "f32": 157.3e12}  # MI355X vector ALU FLOP/s (dense, published)
+KERNEL_NAME = {1: "k_burst", 2: "k_burst_x"}  # by neighbour exchange (LDS, in-wave)
 
 
 def workload(name):
@@ -31,6 +32,86 @@ def workload(name):
     return W.config2(), ("tanh-stretched unit square (beta 2.5), 65x65 macro nodes, 17x17 "
                          "micro points per patch, eps 1e-3, 8 random Fourier modes for D and v, "
                          "source (1 + sin 4 pi t) g")
+
+
+BURST_SOURCES = ["pd_burst.inc", "pd_internal.h", "pd_burst_x_f64.hip", "pd_burst_x_f32.hip",
+                 "pd_burst_lds_f64.hip", "pd_burst_lds_f32.hip"]
+
+
+def burst_source_hash():
+    """SHA-256 over the burst kernels' sources: a traffic figure taken from counters is
+    valid only for the code it was measured on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in BURST_SOURCES:
+        with open(os.path.join(ROOT, "paper_2405_08764_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_file(kernel, workload, precision):
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_hbm_traffic.txt")
+
+
+def read_traffic(kernel, workload, precision, shape):
+    """HBM bytes per launch from the committed counter summary, or None when there is
+    none for this kernel, workload and launch shape, or the kernel changed since."""
+    path = traffic_file(kernel, workload, precision)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != burst_source_hash() or kv.get("shape") != shape:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def pmc_summary(fetch_csv, write_csv, kernel_prefix, calib_mib, out, command, workload,
+                precision, shape):
+    """Per-launch HBM traffic of a kernel from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, both in KiB per dispatch), each scaled by what the same counter reads for
+    the calibration kernel of known traffic (calib_mib MiB read and written)."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals, cal = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            v = float(r["Counter_Value"]) * 1024.0
+            if kernel_prefix in name:
+                vals.append(v)
+            elif "MulFunctor" in name or ("elementwise_kernel" in name and "Mul" in name):
+                cal.append(v)
+        if not vals or not cal:
+            raise SystemExit(f"{path}: no {counter} rows for {kernel_prefix} or calibration")
+        return sum(vals) / len(vals), max(cal), len(vals)
+
+    known = calib_mib * float(1 << 20)
+    f_raw, f_cal, nf = per_kernel(fetch_csv, "FETCH_SIZE")
+    w_raw, w_cal, nw = per_kernel(write_csv, "WRITE_SIZE")
+    ff, fw = known / f_cal, known / w_cal
+    total = f_raw * ff + w_raw * fw
+    with open(out, "w") as fh:
+        fh.write(f"# HBM traffic of {kernel_prefix} ({workload}, {precision}) from rocprofv3 "
+                 "counters\n")
+        fh.write(f"# command (FETCH_SIZE pass; the WRITE_SIZE pass is the same with "
+                 f"--pmc WRITE_SIZE):\n#   {command}\n")
+        fh.write(f"# calibration: torch elementwise multiply reading and writing {calib_mib} "
+                 "MiB; counter scale = known bytes / counted bytes\n")
+        fh.write(f"kernel: {kernel_prefix}\nworkload: {workload}\nprecision: {precision}\n"
+                 f"shape: {shape}\n")
+        fh.write(f"dispatches: {nf} (fetch), {nw} (write)\n")
+        fh.write(f"fetch_raw_bytes_per_launch: {f_raw:.6e}\nfetch_scale: {ff:.4f}\n")
+        fh.write(f"write_raw_bytes_per_launch: {w_raw:.6e}\nwrite_scale: {fw:.4f}\n")
+        fh.write(f"hbm_bytes_per_launch: {total:.6e}\n")
+        fh.write(f"source_sha256: {burst_source_hash()}\n")
+    print(open(out).read())
 
 
 def cpu_baseline(prob, budget_s, steps_cap):
@@ -67,7 +148,27 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the heuristic launch shape instead of timing the candidates")
+    ap.add_argument("--shape", default=None,
+                    help="force the launch shape 'exchange,cols,rows,patches_per_block' "
+                         "(exchange 1 = LDS, 2 = in-wave); implies --no-autotune")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (twice), the reference "
+                         "kernel for scaling HBM byte counters")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic summary of the burst kernel from two "
+                         "rocprofv3 --pmc counter CSVs (no GPU needed) and exit")
+    ap.add_argument("--pmc-shape", default="", help="launch shape the counters were taken at")
+    ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
+    if args.pmc_summary:
+        kernel = "k_burst_x" if args.pmc_shape.startswith("2,") else "k_burst"
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], kernel + "<",
+                    args.calibrate_copy or 256,
+                    traffic_file(kernel, args.workload, args.precision), args.pmc_command,
+                    args.workload, args.precision, args.pmc_shape)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for {max(args.gpus, world)}); the "
@@ -86,6 +187,15 @@ def main():
     with torch.cuda.stream(stream):
         g = pd.Grid(prob, precision=args.precision)
         U = g.initial()
+        tuned_ms = None
+        if args.shape:
+            xch, cols, rows, ppb = (int(v) for v in args.shape.split(","))
+            g.set_option(pd.OPT_EXCHANGE, xch)
+            g.set_option(pd.OPT_COLS_PER_LANE, cols)
+            g.set_option(pd.OPT_ROWS_PER_LANE, rows)
+            g.set_option(pd.OPT_PATCHES_PER_BLOCK, ppb)
+        elif not args.no_autotune:
+            tuned_ms = g.autotune(U, reps=5)
         g.solve(U, n_steps=max(args.warmup, 16))
         g.sync()
         per_step = W.updates_per_step(prob)
@@ -108,12 +218,35 @@ def main():
         torch.cuda.synchronize()
         kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
         info = g.query()
+        if args.calibrate_copy:
+            # A plain streaming kernel of known traffic: read MIB MiB, write MIB MiB
+            # (torch's vectorized elementwise multiply by one).
+            n = args.calibrate_copy * (1 << 20) // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(2):
+                torch.mul(src, 1.0, out=dst)
+            torch.cuda.synchronize()
+            del src, dst
 
     ns = sum(1 for (tf, _, _) in prob["src"] if tf[0] != "const")
-    flops_per_update = 2 * (5 + ns)  # 5 stencil FMAs + one per time-dependent source term
+    # Algorithmic work of one nano update of the scheme with pre-scaled coefficients: two
+    # neighbour sums, two -2u FMAs, two diffusion FMAs, two upwind differences, two
+    # convection FMAs, the reaction FMA, the source add and the +u add (7 FMA + 6 ADD).
+    flops_per_update = 20
+    # What the kernel issues instead: the 5-point stencil with folded weights, the
+    # constant forcing and one FMA per time-dependent source term.
+    issued_flops_per_update = 2 * (5 + ns)
     achieved = flops_per_update * per_step / kern_s
+    # Algorithmic HBM bytes of one fused launch: every coefficient plane once (alpha,
+    # gamma, nu, omega, phi and the source terms' spatial parts), the macro field once,
+    # one new value per patch node.
+    n_src = len(prob["src"])
+    alg_bytes = (5 + n_src) * info.n_points * 8 + info.n_xi * info.n_eta * 8 + info.n_patches * 8
     peak = PEAK[args.precision]
     value = per_step * args.steps / el
+    shape = f"{info.exchange},{info.cols_per_lane},{info.rows_per_lane},{info.patches_per_block}"
+    traffic = read_traffic(KERNEL_NAME[info.exchange], args.workload, args.precision, shape)
     out = {
         "metric": "patch-point updates/s (and macro steps/s) of the plain GPU scheme",
         "value": value,
@@ -133,13 +266,19 @@ def main():
                    "dt_macro": t["dt_macro"], "dt_micro": t["dt_micro"],
                    "updates_per_step": per_step,
                    "launch": {"rows_per_lane": info.rows_per_lane,
+                              "cols_per_lane": info.cols_per_lane,
                               "patches_per_block": info.patches_per_block,
-                              "block_threads": info.block_threads}},
+                              "block_threads": info.block_threads,
+                              "exchange": "in-wave" if info.exchange == 2 else "lds",
+                              "autotuned": bool(info.tuned), "tuned_ms": tuned_ms}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_burst (fused macro step)",
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "algorithmic_bytes": alg_bytes,
+                     "kernel": KERNEL_NAME[info.exchange] + " (fused macro step)",
                      "kernel_ms": kern_s * 1e3,
-                     "flops_per_update": flops_per_update},
+                     "flops_per_update": flops_per_update,
+                     "issued_flops_per_update": issued_flops_per_update,
+                     "issued_frac": issued_flops_per_update * per_step / kern_s / peak},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, steps_cap=50)

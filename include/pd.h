@@ -130,6 +130,8 @@ typedef struct {
   int32_t rows_per_lane, patches_per_block, block_threads; /* current launch shape     */
   int32_t cols_per_lane;
   int32_t exchange;          /* 1: neighbours through LDS, 2: inside one wave (DPP)   */
+  int32_t tuned;             /* 1 once pd_autotune chose the launch shape               */
+  double tuned_ms;           /* its measured time per fused step (ms), else 0           */
 } pd_info;
 
 typedef struct pd_grid_s* pd_grid;
@@ -212,6 +214,20 @@ pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
 #define PD_OPT_COLS_PER_LANE 5
 #define PD_OPT_EXCHANGE 6
 pd_status pd_set_option(pd_grid g, int32_t option, int64_t value);
+
+/* Launch-shape autotuner of the fused step (not in the paper: a property of this library).
+ * Times every launch shape allowed by the current options (exchange, columns and rows per
+ * lane, patches per block, block size) on the actual problem with HIP events: `reps`
+ * fused steps from U (read only; results go to the workspace's second macro buffer, so no
+ * pd_solve of this grid may be in flight), then keeps the fastest.  A process-wide cache
+ * keyed by the patch count and size, precision, time-dependent source count and n_t
+ * answers repeated calls without timing unless flags has PD_TUNE_FORCE.  best_ms (may be
+ * NULL) receives the measured time per step.  Synchronises `stream`.  Errors as
+ * pd_patch_step; PD_ENONFINITE if a timed step produced a non-finite value. */
+#define PD_TUNE_FORCE 1
+pd_status pd_autotune(pd_grid g, const double* U, double t_n, double dt_macro,
+                      double dt_micro, int32_t n_t, int32_t reps, uint32_t flags,
+                      double* best_ms, void* stream);
 
 const char* pd_last_error(void);
 

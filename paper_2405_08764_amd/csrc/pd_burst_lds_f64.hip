@@ -3,12 +3,12 @@
 #include "pd_burst.inc"
 
 namespace pdk {
-hipError_t launch_time_table(const SrcInfo& src, const Clock* clk, double t_n, double dt,
-                             int n_t, double* out, hipStream_t s) {
+hipError_t launch_time_table(const SrcInfo& src, double t_n, double dt, int n_t, double* out,
+                             hipStream_t s) {
   const int n = src.ns * n_t;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_time_table, dim3((n + 255) / 256), dim3(256), 0, s, src, clk, t_n, dt,
-                     n_t, out);
+  hipLaunchKernelGGL(k_time_table, dim3((n + 255) / 256), dim3(256), 0, s, src, t_n, dt, n_t,
+                     out);
   return hipGetLastError();
 }
 

@@ -293,37 +293,52 @@ __global__ void k_limits_final(const double* __restrict__ partial, int nblocks,
   out[1] = hi;
 }
 
-__device__ inline bool is_boundary(const Geo& g, int i, int j) {
-  return j == 0 || j == g.n_eta - 1 || (!g.periodic && (i == 0 || i == g.n_xi - 1));
-}
 
 // Dirichlet data u_b(t) on the boundary nodes (eq. CDR_Com_IC_BCs, eq. Ann_C_IC_BCs).
-// One block; with a clock the time is t0 + (n + 1) dt and the clock advances afterwards.
-__global__ void k_boundary(Geo g, const pd_coeff_desc* __restrict__ desc, double* U, double t,
-                           Clock* clk, int advance) {
-  double* dst = U;
-  if (clk) {
-    const long long n = clk->n;
-    t = clk->t0 + (double)(n + 1) * clk->dt;
-    dst = clk->buf[(n + 1) & 1];
-  }
-  const int nb_rows = 2 * g.n_xi;                       // eta = eta0 and eta1 rows
-  const int nb_cols = g.periodic ? 0 : 2 * (g.n_eta - 2);
-  for (int q = threadIdx.x; q < nb_rows + nb_cols; q += blockDim.x) {
+__global__ void k_boundary(Geo g, const pd_coeff_desc* __restrict__ desc, double* U, double t) {
+  const int nb = boundary_count(g);
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
     int i, j;
-    if (q < nb_rows) {
-      i = q % g.n_xi;
-      j = q < g.n_xi ? 0 : g.n_eta - 1;
-    } else {
-      const int r = q - nb_rows;
-      j = 1 + r / 2;
-      i = (r & 1) ? g.n_xi - 1 : 0;
-    }
-    dst[j * g.n_xi + i] = boundary_at(g, *desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, t);
+    boundary_node(g, q, i, j);
+    U[j * g.n_xi + i] = boundary_at(g, *desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, t);
   }
-  if (clk && advance) {
-    __syncthreads();
-    if (threadIdx.x == 0) clk->n = clk->n + 1;
+}
+
+// First node of a graph replay of S macro steps: macro steps base .. base+S-1 with base =
+// the clock's step count.  Fills the time factors of their bursts,
+// ttab[k][j][s] = T_j(t_n + s dt_micro) with t_n = t0 + (base + k) dt, and the Dirichlet
+// values at their end times, bvals[k][q] = u_b(node q, t0 + (base + k + 1) dt); the burst
+// of step k reads entry k of both.  The last block to finish advances the clock by S (every
+// block has read it by then).
+__global__ void k_replay(Geo g, SrcInfo src, const pd_coeff_desc* __restrict__ desc,
+                         Clock* clk, int S, int n_t, double dt_micro, double* __restrict__ ttab,
+                         double* __restrict__ bvals) {
+  const long long base = clk->next;
+  const double t0 = clk->t0, dt = clk->dt;
+  const int per = src.ns * n_t, nb = boundary_count(g);
+  const int stride = gridDim.x * blockDim.x, first = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int e = first; e < S * per; e += stride) {
+    const int k = e / per, r = e - k * per;
+    const int j = r / n_t, s = r - j * n_t;
+    const double t_n = t0 + (double)(base + k) * dt;
+    ttab[e] = time_factor(src, j, t_n + (double)s * dt_micro);
+  }
+  for (int e = first; e < S * nb; e += stride) {
+    const int k = e / nb, q = e - k * nb;
+    int i, j;
+    boundary_node(g, q, i, j);
+    bvals[e] = boundary_at(g, *desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta,
+                           t0 + (double)(base + k + 1) * dt);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&clk->done, 1u) == gridDim.x - 1) {
+      clk->base = base;
+      clk->next = base + S;
+      clk->done = 0u;
+      __threadfence();
+    }
   }
 }
 
@@ -338,7 +353,9 @@ __global__ void k_clock_init(Clock* clk, double t0, double dt, double* b0, doubl
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     clk->t0 = t0;
     clk->dt = dt;
-    clk->n = 0;
+    clk->base = 0;
+    clk->next = 0;
+    clk->done = 0u;
     clk->buf[0] = b0;
     clk->buf[1] = b1;
   }
@@ -366,9 +383,19 @@ hipError_t launch_limits(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
 }
 
 hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
-                           Clock* clk, int advance_clock, hipStream_t s) {
-  hipLaunchKernelGGL(k_boundary, dim3(1), dim3(256), 0, s, g, dev_desc, U, t, clk,
-                     advance_clock);
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_boundary, dim3(1), dim3(256), 0, s, g, dev_desc, U, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_replay(const Geo& g, const SrcInfo& src, const pd_coeff_desc* dev_desc,
+                         Clock* clk, int S, int n_t, double dt_micro, double* ttab,
+                         double* bvals, hipStream_t s) {
+  const long long work = (long long)S * (src.ns * n_t + boundary_count(g));
+  long long blocks = (work + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 128 ? 128 : blocks);
+  hipLaunchKernelGGL(k_replay, dim3((unsigned)blocks), dim3(256), 0, s, g, src, dev_desc, clk,
+                     S, n_t, dt_micro, ttab, bvals);
   return hipGetLastError();
 }
 

@@ -8,7 +8,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "pd_internal.h"
@@ -65,6 +68,8 @@ pd_status hip_fail(hipError_t e, const char* where) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 constexpr int NB_LIM = 512;  // blocks of the stability-bound reduction
+constexpr int MAX_REPLAY = 16;                 // macro steps per pd_solve graph replay
+constexpr size_t TT_CAP = 2 * (size_t)MAX_NT;  // time-factor table entries
 
 // Micro offsets: m points span the edge h symmetrically, edges included.
 double micro_off(double h, int m, int k) {
@@ -104,7 +109,7 @@ struct pd_grid_s {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_coef = 0, off_pmap = 0, off_tab = 0, off_desc = 0, off_V = 0, off_flag = 0,
-         off_clock = 0, off_part = 0, off_lim = 0, off_ttab = 0, need = 0;
+         off_clock = 0, off_part = 0, off_lim = 0, off_ttab = 0, off_bval = 0, need = 0;
   // coefficients
   bool coeffs_set = false;
   pd_coeff_desc cd{};
@@ -129,6 +134,9 @@ struct pd_grid_s {
   int g_nt = 0;
   double* g_U = nullptr;
   int g_R = 0, g_C = 0, g_ppb = 0, g_threads = 0, g_xch = 0;
+  // autotuner result
+  int tuned = 0;
+  double tuned_ms = 0.0;
 
   double* coef() { return reinterpret_cast<double*>(ws + off_coef); }
   int* dpmap() { return reinterpret_cast<int*>(ws + off_pmap); }
@@ -140,6 +148,7 @@ struct pd_grid_s {
   double* part() { return reinterpret_cast<double*>(ws + off_part); }
   double* lim() { return reinterpret_cast<double*>(ws + off_lim); }
   double* ttab() { return reinterpret_cast<double*>(ws + off_ttab); }
+  double* bvals() { return reinterpret_cast<double*>(ws + off_bval); }
 };
 
 namespace {
@@ -154,9 +163,10 @@ void drop_graph(pd_grid g) {
 
 // Launch shape of the burst: C columns x R rows per lane, ppb patches per block, and the
 // neighbour exchange.  Candidates are ranked by the useful fraction of the lane slots
-// (idle lanes and padding points are wasted VALU issue); on ties, the in-wave exchange
-// (no LDS traffic in the nano-step loop), then wider lane blocks (fewer exchanged values
-// per point), then smaller blocks.  pd_autotune replaces this guess by measurement.
+// (idle lanes and padding points are wasted VALU issue), weighted 1.5x for the in-wave
+// exchange (no LDS traffic and no barrier in the nano-step loop; measured about that much
+// faster per lane slot); on ties, wider lane blocks (fewer exchanged values per point),
+// more rows, then smaller blocks.  pd_autotune replaces this guess by measurement.
 struct Shape {
   int R, C, xch, ppb, threads;
   double score;
@@ -185,7 +195,8 @@ bool next_shape(pd_grid g, int xch_only, bool split, std::vector<Shape>& out) {
           if (burst_lds_bytes(g->d.precision, R, C, xch, threads, ppb, mx, me, g->src.ns) > 65536)
             continue;
           const double eff = (double)ppb * mx * me / ((double)threads * R * C);
-          const double score = eff + 2e-3 * (xch == XCH_LANES) + 1e-3 * (C - 1) - 1e-5 * threads;
+          const double score = eff * (xch == XCH_LANES ? 1.5 : 1.0) + 1e-3 * (C - 1) + 1e-4 * R -
+                               1e-5 * threads;
           out.push_back({R, C, xch, ppb, threads, score});
         }
       }
@@ -204,6 +215,18 @@ void apply_shape(pd_grid g, const Shape& b) {
   g->lds = burst_lds_bytes(g->d.precision, b.R, b.C, b.xch, b.threads, b.ppb, g->g.m_xi,
                            g->g.m_eta, g->src.ns);
 }
+
+// Process-wide cache of autotuned shapes.
+struct TuneKey {
+  int P, mx, me, precision, ns, n_t, conv, xch, C, R, ppb, threads;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(P, mx, me, precision, ns, n_t, conv, xch, C, R, ppb, threads) <
+           std::tie(o.P, o.mx, o.me, o.precision, o.ns, o.n_t, o.conv, o.xch, o.C, o.R, o.ppb,
+                    o.threads);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<Shape, double>> g_tune;
 
 void choose_shape(pd_grid g) {
   std::vector<Shape> c;
@@ -420,7 +443,8 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
   g->off_clock = o; o = align256(o + sizeof(Clock));
   g->off_part = o; o = align256(o + 2 * NB_LIM * sizeof(double));
   g->off_lim = o; o = align256(o + 2 * sizeof(double));
-  g->off_ttab = o; o = align256(o + 2 * (size_t)MAX_NT * sizeof(double));
+  g->off_ttab = o; o = align256(o + TT_CAP * sizeof(double));
+  g->off_bval = o; o = align256(o + (size_t)MAX_REPLAY * boundary_count(G) * sizeof(double));
   g->need = o;
   choose_shape(g);
   *out = g;
@@ -458,6 +482,8 @@ pd_status pd_query(pd_grid g, pd_info* out) {
   I.exchange = g->xch;
   I.patches_per_block = g->ppb;
   I.block_threads = g->threads;
+  out->tuned = g->tuned;
+  out->tuned_ms = g->tuned_ms;
   return PD_OK;
 }
 
@@ -559,8 +585,7 @@ pd_status pd_micro_burst(pd_grid g, double* state, const double* edge, double t_
   a.state = state;
   a.edge = edge;
   a.ppb = g->sppb;
-  HIPCHK(launch_time_table(g->src, nullptr, t_n, dt, n_t, g->ttab(),
-                           static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_time_table(g->src, t_n, dt, n_t, g->ttab(), static_cast<hipStream_t>(stream)));
   HIPCHK(launch_burst(g->d.precision, g->sR, g->sC, XCH_LDS, MODE_SPLIT, a, g->sblocks,
                       g->sthreads, g->slds, static_cast<hipStream_t>(stream)));
   return PD_OK;
@@ -594,10 +619,10 @@ pd_status pd_macro_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
     a.Unew = U_np1;
     a.dt_macro = dt_macro;
     a.tau = tau;
-    HIPCHK(launch_time_table(g->src, nullptr, t_n, dt, n_t, g->ttab(), s));
+    HIPCHK(launch_time_table(g->src, t_n, dt, n_t, g->ttab(), s));
     HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds, s));
   }
-  HIPCHK(launch_boundary(g->g, g->ddesc(), U_np1, t_n + dt_macro, nullptr, 0, s));
+  HIPCHK(launch_boundary(g->g, g->ddesc(), U_np1, t_n + dt_macro, s));
   return PD_OK;
 }
 
@@ -613,8 +638,7 @@ pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
   a.Unew = U_np1;
   a.dt_macro = dt_macro;
   a.tau = n_t * dt;
-  HIPCHK(launch_time_table(g->src, nullptr, t_n, dt, n_t, g->ttab(),
-                           static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_time_table(g->src, t_n, dt, n_t, g->ttab(), static_cast<hipStream_t>(stream)));
   HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds,
                       static_cast<hipStream_t>(stream)));
   return PD_OK;
@@ -625,7 +649,7 @@ pd_status pd_apply_boundary(pd_grid g, double* U, double t, void* stream) {
   if (st) return st;
   if (!U) return fail(PD_EINVAL, "null U");
   HIPCHK(hipSetDevice(g->d.device));
-  HIPCHK(launch_boundary(g->g, g->ddesc(), U, t, nullptr, 0, static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_boundary(g->g, g->ddesc(), U, t, static_cast<hipStream_t>(stream)));
   return PD_OK;
 }
 
@@ -650,7 +674,13 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
   a.dt_macro = dt_macro;
   a.tau = tau;
   a.clk = g->clock();
-  const int S = n_steps < 16 ? n_steps : 16;  // macro steps per graph replay
+  // Macro steps per graph replay: one k_replay node (clock, time factors and Dirichlet
+  // values of all S steps), then one fused burst per step.
+  const size_t per = (size_t)g->src.ns * n_t;
+  int S = n_steps < MAX_REPLAY ? n_steps : MAX_REPLAY;
+  while (S > 1 && S * per > TT_CAP) --S;
+  const int nb = boundary_count(g->g);
+  a.nb = nb;
   const bool reuse = g->gexec && g->g_steps == S && g->g_dtm == dt_macro && g->g_dt == dt &&
                      g->g_nt == n_t && g->g_U == U && g->g_R == g->R && g->g_C == g->C &&
                      g->g_ppb == g->ppb && g->g_threads == g->threads && g->g_xch == g->xch;
@@ -659,20 +689,27 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     HIPCHK(hipStreamWaitEvent(w, g->ev_in, 0));
   }
   HIPCHK(launch_clock_init(g->clock(), t0, dt_macro, U, g->V(), w));
+  auto steps = [&](int count) -> hipError_t {
+    hipError_t e = launch_replay(g->g, g->src, g->ddesc(), g->clock(), count, n_t, dt,
+                                 g->ttab(), g->bvals(), w);
+    for (int k = 0; k < count && e == hipSuccess; ++k) {
+      a.k = k;
+      a.ttab = g->ttab() + k * per;
+      a.bvals = g->bvals() + (size_t)k * nb;
+      e = launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks,
+                       g->threads, g->lds, w);
+    }
+    return e;
+  };
   if (!reuse) {
     drop_graph(g);
     HIPCHK(hipStreamBeginCapture(w, hipStreamCaptureModeThreadLocal));
-    for (int q = 0; q < S; ++q) {
-      hipError_t e0 = launch_time_table(g->src, g->clock(), t0, dt, n_t, g->ttab(), w);
-      hipError_t e1 = e0 != hipSuccess ? e0 : launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a,
-                                                           g->blocks, g->threads, g->lds, w);
-      hipError_t e2 = launch_boundary(g->g, g->ddesc(), nullptr, 0.0, g->clock(), 1, w);
-      if (e1 != hipSuccess || e2 != hipSuccess) {
-        hipGraph_t junk = nullptr;
-        (void)hipStreamEndCapture(w, &junk);
-        if (junk) (void)hipGraphDestroy(junk);
-        return hip_fail(e1 != hipSuccess ? e1 : e2, "graph capture");
-      }
+    const hipError_t e = steps(S);
+    if (e != hipSuccess) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(w, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      return hip_fail(e, "graph capture");
     }
     HIPCHK(hipStreamEndCapture(w, &g->graph));
     HIPCHK(hipGraphInstantiate(&g->gexec, g->graph, nullptr, nullptr, 0));
@@ -689,17 +726,92 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
   }
   const int reps = n_steps / S, rem = n_steps - reps * S;
   for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(g->gexec, w));
-  for (int q = 0; q < rem; ++q) {
-    HIPCHK(launch_time_table(g->src, g->clock(), t0, dt, n_t, g->ttab(), w));
-    HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds, w));
-    HIPCHK(launch_boundary(g->g, g->ddesc(), nullptr, 0.0, g->clock(), 1, w));
-  }
+  if (rem) HIPCHK(steps(rem));
   if (n_steps & 1)
     HIPCHK(hipMemcpyAsync(U, g->V(), (size_t)g->g.n_xi * g->g.n_eta * sizeof(double),
                           hipMemcpyDeviceToDevice, w));
   if (own) {
     HIPCHK(hipEventRecord(g->ev_out, w));
     HIPCHK(hipStreamWaitEvent(s, g->ev_out, 0));
+  }
+  return PD_OK;
+}
+
+pd_status pd_autotune(pd_grid g, const double* U, double t_n, double dt_macro, double dt,
+                      int32_t n_t, int32_t reps, uint32_t flags, double* best_ms,
+                      void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U) return fail(PD_EINVAL, "null U");
+  if ((st = guard_macro(g, dt_macro, dt, n_t))) return st;
+  if (reps < 1) reps = 5;
+  HIPCHK(hipSetDevice(g->d.device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const TuneKey key{g->g.P, g->g.m_xi, g->g.m_eta, g->d.precision, g->src.ns, n_t,
+                    g->g.conv, g->opt_xch, g->opt_C, g->opt_R, g->opt_ppb, g->opt_threads};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end() && !(flags & PD_TUNE_FORCE)) {
+      apply_shape(g, it->second.first);
+      g->tuned = 1;
+      g->tuned_ms = it->second.second;
+      if (best_ms) *best_ms = g->tuned_ms;
+      return PD_OK;
+    }
+  }
+  std::vector<Shape> cand;
+  if (!next_shape(g, g->opt_xch, false, cand)) return fail(PD_EINVAL, "no launch shape to tune");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto cleanup = [&]() {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  };
+  const Shape keep{g->R, g->C, g->xch, g->ppb, g->threads, 0.0};
+  double best = 1e300;
+  Shape bs = keep;
+  hipError_t e = launch_time_table(g->src, t_n, dt, n_t, g->ttab(), s);
+  for (size_t q = 0; q < cand.size() && e == hipSuccess; ++q) {
+    apply_shape(g, cand[q]);
+    BurstArgs a = base_args(g, t_n, dt, n_t);
+    a.U = U;
+    a.Unew = g->V();
+    a.dt_macro = dt_macro;
+    a.tau = n_t * dt;
+    auto launch = [&]() {
+      return launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks,
+                          g->threads, g->lds, s);
+    };
+    if ((e = launch()) != hipSuccess) break;  // warm-up (code load, caches)
+    if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+    const double per = (double)ms / reps;
+    if (per < best) {
+      best = per;
+      bs = cand[q];
+    }
+  }
+  cleanup();
+  apply_shape(g, e == hipSuccess ? bs : keep);
+  if (e != hipSuccess) return hip_fail(e, "pd_autotune");
+  g->tuned = 1;
+  g->tuned_ms = best;
+  if (best_ms) *best_ms = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {bs, best};
+  }
+  int flag = 0;
+  HIPCHK(hipMemcpy(&flag, g->flag(), sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    HIPCHK(hipMemset(g->flag(), 0, sizeof(int)));
+    return fail(PD_ENONFINITE, "a timed step produced a non-finite value");
   }
   return PD_OK;
 }
@@ -770,6 +882,8 @@ pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
       break;
     default: return fail(PD_EINVAL, "unknown option");
   }
+  g->tuned = 0;
+  g->tuned_ms = 0.0;
   choose_shape(g);
   if (!g->R) {
     g->opt_R = 0;

@@ -45,12 +45,15 @@ __host__ __device__ inline TabOff tab_off(int mx, int me) {
   return t;
 }
 
-// Device-side clock of pd_solve: macro step n at time t0 + n dt; the fused kernels
-// read the macro field from buf[n & 1] and write buf[(n + 1) & 1].
+// Device-side clock of pd_solve.  A replay of the captured steps starts with k_replay,
+// which sets base = next (macro steps done so far) and advances next; step k of the
+// replay is macro step n = base + k at time t0 + n dt, reading the macro field from
+// buf[n & 1] and writing buf[(n + 1) & 1].
 struct Clock {
   double t0, dt;
-  long long n;
+  long long base, next;
   double* buf[2];
+  unsigned int done;  // blocks of k_replay finished (the last one advances the clock)
 };
 
 // Time factors and the constant part of the source, packed for kernel arguments.
@@ -63,6 +66,30 @@ struct SrcInfo {
   int plane_c[PD_MAXTERM];
   double ca[PD_MAXTERM];
 };
+
+// Time factor T_j(t) of time-dependent source term j.
+__device__ inline double time_factor(const SrcInfo& src, int j, double t) {
+  if (src.ttype[j] == PD_T_EXP) return src.ta[j] * exp(src.tb[j] * t);
+  if (src.ttype[j] == PD_T_SIN) return src.ta[j] + src.tb[j] * sin(src.tc[j] * t);
+  return src.ta[j];
+}
+
+// Dirichlet nodes in a fixed order: the eta = eta0 and eta = eta1 rows, then (when xi is
+// not periodic) the xi = xi0 and xi = xi1 columns between them, alternating.
+__host__ __device__ inline int boundary_count(const Geo& g) {
+  return 2 * g.n_xi + (g.periodic ? 0 : 2 * (g.n_eta - 2));
+}
+__host__ __device__ inline void boundary_node(const Geo& g, int q, int& i, int& j) {
+  const int nb_rows = 2 * g.n_xi;
+  if (q < nb_rows) {
+    i = q % g.n_xi;
+    j = q < g.n_xi ? 0 : g.n_eta - 1;
+  } else {
+    const int r = q - nb_rows;
+    j = 1 + r / 2;
+    i = (r & 1) ? g.n_xi - 1 : 0;
+  }
+}
 
 enum { MODE_SPLIT = 0, MODE_FUSED = 1 };
 // Neighbour exchange of the burst: through LDS (any block size) or inside one wave
@@ -82,8 +109,11 @@ struct BurstArgs {
   // fused mode
   const double* U;        // U_n
   double* Unew;           // U_{n+1} (patch nodes)
-  const Clock* clk;       // non-null: take t_n and the buffers from the device clock
+  const Clock* clk;       // non-null: macro step clk->base + k, buffers from the clock
+  int k;                  //   (step within the graph replay)
   const double* ttab;     // [ns][n_t] time factors T_j(t_n + s dt)
+  const double* bvals;    // non-null: Dirichlet values at t_n + dt_macro, written to Unew
+  int nb;                 //   (boundary_count entries)
   double t_n, dt, dt_macro, tau;
   int n_t;
   int ppb;                // patches per block
@@ -97,7 +127,12 @@ hipError_t launch_limits(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
                          const double* coef, double* partial, int nblocks, double* out,
                          hipStream_t s);
 hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
-                           Clock* clk, int advance_clock, hipStream_t s);
+                           hipStream_t s);
+// Start of a graph replay of S macro steps: advances the clock and fills the time factors
+// ttab[S][ns][n_t] and the Dirichlet values bvals[S][nb] of those steps.
+hipError_t launch_replay(const Geo& g, const SrcInfo& src, const pd_coeff_desc* dev_desc,
+                         Clock* clk, int S, int n_t, double dt_micro, double* ttab,
+                         double* bvals, hipStream_t s);
 hipError_t launch_initial(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
                           hipStream_t s);
 hipError_t launch_clock_init(Clock* clk, double t0, double dt, double* b0, double* b1,
@@ -109,8 +144,8 @@ hipError_t launch_macro_update(const Geo& g, const int* pmap, const double* U,
                                const double* Ubar, double* Unew, double dt_macro, double tau,
                                int* flag, hipStream_t s);
 // Time factors of the time-dependent source terms for one burst.
-hipError_t launch_time_table(const SrcInfo& src, const Clock* clk, double t_n, double dt,
-                             int n_t, double* out, hipStream_t s);
+hipError_t launch_time_table(const SrcInfo& src, double t_n, double dt, int n_t, double* out,
+                             hipStream_t s);
 constexpr int MAX_NT = 65536;  // nano steps per burst (size of the time-factor table)
 // Burst kernels: precision PD_F64/PD_F32, C columns x R rows per lane, exchange, mode.
 hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const BurstArgs& a,

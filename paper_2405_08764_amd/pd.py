@@ -23,6 +23,7 @@ FN = {"sin": 0, "cos": 1, "exp": 2, "poly": 3}
 TF = {"const": 0, "exp": 1, "sin": 2}
 OPT_ALLOW_UNSTABLE, OPT_ROWS_PER_LANE, OPT_PATCHES_PER_BLOCK, OPT_BLOCK_THREADS = 1, 2, 3, 4
 OPT_COLS_PER_LANE, OPT_EXCHANGE = 5, 6
+TUNE_FORCE = 1
 
 STATUS = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ESTATE", -3: "PD_EUNSTABLE", -4: "PD_EDEVICE",
           -5: "PD_ENONFINITE", -6: "PD_ENOMEM"}
@@ -80,7 +81,8 @@ class Info(C.Structure):
                 ("dt_macro_limit", C.c_double), ("coefficients_set", C.c_int32),
                 ("n_time_sources", C.c_int32), ("rows_per_lane", C.c_int32),
                 ("patches_per_block", C.c_int32), ("block_threads", C.c_int32),
-                ("cols_per_lane", C.c_int32), ("exchange", C.c_int32)]
+                ("cols_per_lane", C.c_int32), ("exchange", C.c_int32),
+                ("tuned", C.c_int32), ("tuned_ms", C.c_double)]
 
 
 EXPORTS = {
@@ -107,6 +109,9 @@ EXPORTS = {
     "pd_get_tables": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pd_copy_coefficients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_set_option": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int64]),
+    "pd_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                C.c_int32, C.c_int32, C.c_uint32, C.POINTER(C.c_double),
+                                C.c_void_p]),
     "pd_last_error": (C.c_char_p, []),
 }
 
@@ -322,6 +327,21 @@ class Grid:
             float(t["dt_micro"] if dt_micro is None else dt_micro),
             int(t["n_t"] if n_t is None else n_t), _stream()))
         return out
+
+    def autotune(self, U=None, t_n=None, reps=5, force=False, dt_macro=None, dt_micro=None,
+                 n_t=None):
+        """Time every allowed launch shape of the fused step and keep the fastest; returns
+        the measured ms per step."""
+        t = self.prob["time"]
+        U = self.initial() if U is None else U
+        best = C.c_double(0.0)
+        _check(self.L.pd_autotune(
+            self.h, _ptr(U), float(t["t0"] if t_n is None else t_n),
+            float(t["dt_macro"] if dt_macro is None else dt_macro),
+            float(t["dt_micro"] if dt_micro is None else dt_micro),
+            int(t["n_t"] if n_t is None else n_t), int(reps), TUNE_FORCE if force else 0,
+            C.byref(best), _stream()))
+        return best.value
 
     def apply_boundary(self, U, t):
         _check(self.L.pd_apply_boundary(self.h, _ptr(U), float(t), _stream()))

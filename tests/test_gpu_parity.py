@@ -267,10 +267,14 @@ def test_bitwise_determinism_across_runs_and_launch_shapes(pd, problems):
     assert {k[0] for k in seen} == {1, 2}, seen
 
 
-def test_graph_solve_equals_single_steps_and_resume(pd, problems):
-    """pd_solve (graph replay, device clock) equals repeated pd_macro_step, and a run
-    split in two with the state as checkpoint resumes bit-exactly."""
-    prob = W.with_time(problems["config1"], n_steps=21)
+@pytest.mark.parametrize("name", ["config1", "sec412_sine", "ragged_13x7"])
+def test_graph_solve_equals_single_steps_and_resume(pd, problems, name):
+    """pd_solve (graph replay of one boundary/time-table node and one fused burst per
+    step, device clock, a remainder outside the graph) equals repeated pd_macro_step, and
+    a run split in two with the state as checkpoint resumes bit-exactly."""
+    t = problems[name]["time"]
+    prob = W.with_time(problems[name], n_steps=21,
+                       ratio=t["dt_macro"] / (t["n_t"] * t["dt_micro"]))
     g = pd.Grid(prob)
     t = prob["time"]
     full = g.solve().cpu().numpy()
@@ -282,6 +286,27 @@ def test_graph_solve_equals_single_steps_and_resume(pd, problems):
     U = g.solve(U=U, n_steps=12, t0=t["t0"] + 9 * t["dt_macro"])
     # the clock computes t_n = t0 + n dt; a resumed run starts a new clock at t0 + 9 dt
     np.testing.assert_allclose(U.cpu().numpy(), full, rtol=1e-14, atol=1e-15)
+
+
+def test_autotune_keeps_results_and_caches(pd, problems):
+    """The autotuner times the allowed launch shapes, keeps the fastest (results are
+    bitwise those of any other shape) and answers a second grid of the same kind from its
+    cache."""
+    prob = problems["config2_17x17"]
+    g = pd.Grid(prob)
+    ref = g.solve().cpu().numpy()
+    ms = g.autotune(reps=2, force=True)
+    I = g.query()
+    assert I.tuned == 1 and ms > 0 and I.tuned_ms == ms
+    assert g.solve().cpu().numpy().tobytes() == ref.tobytes()
+    g2 = pd.Grid(prob)
+    assert g2.autotune(reps=2) == ms
+    J = g2.query()
+    assert (J.exchange, J.cols_per_lane, J.rows_per_lane, J.patches_per_block,
+            J.block_threads) == (I.exchange, I.cols_per_lane, I.rows_per_lane,
+                                 I.patches_per_block, I.block_threads)
+    g2.set_option(pd.OPT_EXCHANGE, 1)  # options drop the tuned shape
+    assert g2.query().tuned == 0
 
 
 def test_stability_guard_and_nonfinite_flag(pd, problems):

@@ -229,6 +229,59 @@ pd_status pd_autotune(pd_grid g, const double* U, double t_n, double dt_macro,
                       double dt_micro, int32_t n_t, int32_t reps, uint32_t flags,
                       double* best_ms, void* stream);
 
+/* ----------------------------------------------------------------------------- batches
+ * Many independent problems advanced together (not in the paper: how this library fills
+ * a GPU with many small grids).  Every member keeps its own grid (FP64 bursts,
+ * coefficients set, workspace bound), macro field U (device, [n_eta][n_xi], in/out) and
+ * time parameters.  A batch macro step is one persistent launch in which blocks take
+ * groups of patches of any member from a device work queue (sorted longest first), with
+ * lift, burst, restriction and projection fused as in pd_patch_step and the Dirichlet
+ * nodes written by the same launch; pd_batch_solve replays steps from a HIP graph.  The
+ * result for each member is bitwise that of pd_solve on its grid.  While a batch is in
+ * use its members' workspaces belong to it (their second macro buffer, time-factor and
+ * Dirichlet tables). */
+typedef struct pd_batch_s* pd_batch;
+typedef struct {
+  pd_grid grid;
+  double* U;
+  double t0, dt_macro, dt_micro;
+  int32_t n_t;
+} pd_batch_member;
+typedef struct {
+  int32_t n_members;
+  int32_t n_items;           /* work items of the queue                                 */
+  int32_t blocks;            /* persistent blocks per launch                            */
+  int32_t time_sources;      /* time-dependent source terms the kernel carries (1 or 2)  */
+  size_t workspace_bytes;    /* device bytes pd_batch_bind_workspace needs               */
+  size_t lds_bytes;          /* dynamic LDS per block                                    */
+  int32_t tuned;
+  double tuned_ms;           /* measured time of one batch macro step after tuning (ms)  */
+  int64_t updates_per_step;  /* sum over members of patches x points x n_t               */
+} pd_batch_info;
+/* Validates the members (PD_EINVAL: null grid or U, FP32 grid, bad time parameters;
+ * PD_ESTATE: coefficients or workspace missing; PD_EUNSTABLE as pd_solve) and picks a
+ * launch shape per member from the batch kernel's menu.  Allocates no device memory. */
+pd_status pd_batch_create(const pd_batch_member* members, int32_t n, pd_batch* out);
+pd_status pd_batch_destroy(pd_batch b);
+pd_status pd_batch_query(pd_batch b, pd_batch_info* out);
+/* Device memory for the instance table, the work queue and the shared clock
+ * (>= pd_batch_info.workspace_bytes, 256-byte aligned); PD_ENOMEM if too small. */
+pd_status pd_batch_bind_workspace(pd_batch b, void* dev, size_t bytes);
+/* Menu shape of a member (its index in the kernel's menu and patches per team) and a
+ * way to force one (shape -1 = automatic); PD_EINVAL if the shape cannot hold the
+ * member's patches. */
+pd_status pd_batch_get_shape(pd_batch b, int32_t member, int32_t* shape, int32_t* ppb);
+pd_status pd_batch_set_shape(pd_batch b, int32_t member, int32_t shape);
+/* Autotuner: for each group of members with the same patch size, times every feasible
+ * menu shape in the batch kernel itself (HIP events, `reps` launches) and keeps the
+ * fastest; best_ms (may be NULL) receives the measured time of a whole batch step.
+ * Writes only the members' second macro buffers.  Synchronises `stream`. */
+pd_status pd_batch_autotune(pd_batch b, int32_t reps, double* best_ms, void* stream);
+/* n_steps macro steps of every member from its t0. */
+pd_status pd_batch_solve(pd_batch b, int32_t n_steps, void* stream);
+/* Synchronise and report PD_ENONFINITE if any member's kernels saw a non-finite value. */
+pd_status pd_batch_sync(pd_batch b, void* stream);
+
 const char* pd_last_error(void);
 
 #ifdef __cplusplus

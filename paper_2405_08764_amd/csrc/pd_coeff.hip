@@ -342,6 +342,46 @@ __global__ void k_replay(Geo g, SrcInfo src, const pd_coeff_desc* __restrict__ d
   }
 }
 
+// k_replay for a batch: block i fills instance i's time factors and Dirichlet values for
+// macro steps base .. base+S-1 (base = the shared clock's step count), in the same
+// arithmetic as k_replay (t0 = the instance's t_n field, dt = its dt_macro); the last
+// block advances the clock.
+__global__ void k_batch_replay(const BurstArgs* __restrict__ inst,
+                               const pd_coeff_desc* const* __restrict__ descs, int n, Clock* clk,
+                               int S) {
+  const long long base = clk->next;
+  for (int b = blockIdx.x; b < n; b += gridDim.x) {
+    const BurstArgs& A = inst[b];
+    const int per = A.src.ns * A.n_t, nb = A.nb;
+    const double t0 = A.t_n, dtm = A.dt_macro;
+    double* ttab = const_cast<double*>(A.ttab);
+    double* bv = const_cast<double*>(A.bvals);
+    for (int e = threadIdx.x; e < S * per; e += blockDim.x) {
+      const int k = e / per, r = e - k * per;
+      const int j = r / A.n_t, s = r - j * A.n_t;
+      const double t_n = t0 + (double)(base + k) * dtm;
+      ttab[e] = time_factor(A.src, j, t_n + (double)s * A.dt);
+    }
+    for (int e = threadIdx.x; e < S * nb; e += blockDim.x) {
+      const int k = e / nb, q = e - k * nb;
+      int i, j;
+      boundary_node(A.g, q, i, j);
+      bv[e] = boundary_at(A.g, *descs[b], A.g.xi0 + i * A.g.Dxi, A.g.eta0 + j * A.g.Deta,
+                          t0 + (double)(base + k + 1) * dtm);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&clk->done, 1u) == gridDim.x - 1) {
+      clk->base = base;
+      clk->next = base + S;
+      clk->done = 0u;
+      __threadfence();
+    }
+  }
+}
+
 __global__ void k_initial(Geo g, const pd_coeff_desc* __restrict__ desc, double* U, double t) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.n_xi * g.n_eta) return;
@@ -385,6 +425,13 @@ hipError_t launch_limits(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
 hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_boundary, dim3(1), dim3(256), 0, s, g, dev_desc, U, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_replay(const BurstArgs* inst, const pd_coeff_desc* const* descs, int n,
+                               Clock* clk, int S, hipStream_t s) {
+  const int blocks = n < 1024 ? n : 1024;
+  hipLaunchKernelGGL(k_batch_replay, dim3(blocks), dim3(256), 0, s, inst, descs, n, clk, S);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 // time T").
 #pragma clang fp contract(off)
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -898,3 +899,5 @@ pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
 }
 
 }  // extern "C"
+
+#include "pd_batch_host.inc"

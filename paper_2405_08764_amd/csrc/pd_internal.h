@@ -155,8 +155,9 @@ bool burst_shape_supported(int R, int C);
 // Dynamic LDS bytes of a burst launch: the lane-major exchange tiles (double-buffered,
 // guard of lanes-per-band + 1 words on both sides) or the FP64 lifted tile of the
 // prologue, whichever is larger, then the time-factor chunk and the restriction rows.
-inline size_t burst_lds_bytes(int precision, int R, int C, int xch, int threads, int ppb,
-                              int mx, int me, int ns) {
+__host__ __device__ inline size_t burst_lds_bytes(int precision, int R, int C, int xch,
+                                                  int threads, int ppb, int mx, int me,
+                                                  int ns) {
   const size_t rs = precision == PD_F32 ? 4 : 8;
   const int Lb = (mx + C - 1) / C;
   const size_t nbuf = xch == XCH_LANES ? 1 : 2;
@@ -166,5 +167,42 @@ inline size_t burst_lds_bytes(int precision, int R, int C, int xch, int threads,
   const int TCH = 256;
   return region + (size_t)(ns > 0 ? ns : 1) * TCH * 8 + (size_t)ppb * me * 8 + 64;
 }
+
+// ---------------------------------------------------------------- batched bursts
+// Launch shapes the persistent batch kernel can run: (id, exchange, columns, rows per
+// lane).  In-wave shapes run four single-wave teams per block; LDS shapes one team of
+// the whole block.
+#define PD_BATCH_MENU(X)                                                                 \
+  X(0, XCH_LANES, 1, 3) X(1, XCH_LANES, 1, 5) X(2, XCH_LANES, 1, 6) X(3, XCH_LANES, 1, 7) \
+  X(4, XCH_LANES, 2, 3) X(5, XCH_LDS, 1, 5) X(6, XCH_LDS, 1, 7) X(7, XCH_LDS, 2, 3)
+constexpr int BATCH_MENU = 8;
+constexpr int BATCH_THREADS = 256;
+constexpr int BATCH_WAVES = BATCH_THREADS / 64;
+
+// One unit of the device work queue: ppb patches per team from patch p0 of instance inst
+// (in-wave shapes: BATCH_WAVES teams, p0 + w * ppb for wave w).
+struct BatchItem {
+  int inst, shape, p0, ppb;
+};
+
+struct BatchArgs {
+  const BurstArgs* inst;    // per instance: grid constants, planes, tables, U (buffer 0),
+                            // Unew (buffer 1), t_n = t0, dt, dt_macro, tau, n_t, ttab, bvals
+  const BatchItem* items;   // in queue order
+  int n_items;
+  int* head;                // next item (the last block to finish resets it)
+  unsigned int* exits;      // blocks finished
+  const Clock* clk;         // macro step = clk->base + k (buffers by its parity)
+  int k;                    // step within the graph replay
+  int tuning;               // 1: read buffer 0, write buffer 1, whatever the clock says
+};
+
+// Persistent batch kernel, nsb = 1 or 2 time-dependent source terms at most.
+hipError_t launch_batch(int nsb, const BatchArgs& a, int blocks, size_t lds, hipStream_t s);
+hipError_t batch_blocks_per_cu(int nsb, size_t lds, int* out);
+// Time factors and Dirichlet values of S steps for every instance (one block per
+// instance); the last block advances the clock.
+hipError_t launch_batch_replay(const BurstArgs* inst, const pd_coeff_desc* const* descs, int n,
+                               Clock* clk, int S, hipStream_t s);
 
 }  // namespace pdk

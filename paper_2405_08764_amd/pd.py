@@ -85,6 +85,18 @@ class Info(C.Structure):
                 ("tuned", C.c_int32), ("tuned_ms", C.c_double)]
 
 
+class BatchMember(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("U", C.c_void_p), ("t0", C.c_double),
+                ("dt_macro", C.c_double), ("dt_micro", C.c_double), ("n_t", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("n_members", C.c_int32), ("n_items", C.c_int32), ("blocks", C.c_int32),
+                ("time_sources", C.c_int32), ("workspace_bytes", C.c_size_t),
+                ("lds_bytes", C.c_size_t), ("tuned", C.c_int32), ("tuned_ms", C.c_double),
+                ("updates_per_step", C.c_int64)]
+
+
 EXPORTS = {
     "pd_create_grid": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(C.c_void_p)]),
     "pd_destroy_grid": (C.c_int32, [C.c_void_p]),
@@ -112,6 +124,17 @@ EXPORTS = {
     "pd_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
                                 C.c_int32, C.c_int32, C.c_uint32, C.POINTER(C.c_double),
                                 C.c_void_p]),
+    "pd_batch_create": (C.c_int32, [C.POINTER(BatchMember), C.c_int32, C.POINTER(C.c_void_p)]),
+    "pd_batch_destroy": (C.c_int32, [C.c_void_p]),
+    "pd_batch_query": (C.c_int32, [C.c_void_p, C.POINTER(BatchInfo)]),
+    "pd_batch_bind_workspace": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "pd_batch_get_shape": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]),
+    "pd_batch_set_shape": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32]),
+    "pd_batch_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                      C.c_void_p]),
+    "pd_batch_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "pd_batch_sync": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pd_last_error": (C.c_char_p, []),
 }
 
@@ -359,3 +382,64 @@ class Grid:
 
     def sync(self):
         _check(self.L.pd_sync(self.h, _stream()))
+
+
+class Batch:
+    """Independent grids advanced together by the persistent batch kernel (pd_batch_*).
+
+    grids: Grid objects (FP64, coefficients set); Us: their macro fields (default: each
+    grid's initial data).  Time parameters come from each grid's problem description.
+    The Grid objects are kept alive with the batch (their workspaces are in use).
+    """
+
+    def __init__(self, grids, Us=None):
+        self.L = lib()
+        self.grids = list(grids)
+        self.U = [g.initial() for g in self.grids] if Us is None else list(Us)
+        n = len(self.grids)
+        arr = (BatchMember * n)()
+        for i, (g, U) in enumerate(zip(self.grids, self.U)):
+            t = g.prob["time"]
+            arr[i] = BatchMember(g.h.value, U.data_ptr(), float(t["t0"]), float(t["dt_macro"]),
+                                 float(t["dt_micro"]), int(t["n_t"]))
+        self.h = C.c_void_p()
+        _check(self.L.pd_batch_create(arr, n, C.byref(self.h)))
+        need = self.query().workspace_bytes
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.grids[0].device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        _check(self.L.pd_batch_bind_workspace(self.h, C.c_void_p(base + off), need))
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            self.L.pd_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def query(self):
+        info = BatchInfo()
+        _check(self.L.pd_batch_query(self.h, C.byref(info)))
+        return info
+
+    def shape(self, i):
+        s, p = C.c_int32(), C.c_int32()
+        _check(self.L.pd_batch_get_shape(self.h, i, C.byref(s), C.byref(p)))
+        return s.value, p.value
+
+    def set_shape(self, i, shape):
+        _check(self.L.pd_batch_set_shape(self.h, i, int(shape)))
+
+    def autotune(self, reps=3):
+        best = C.c_double(0.0)
+        _check(self.L.pd_batch_autotune(self.h, int(reps), C.byref(best), _stream()))
+        return best.value
+
+    def solve(self, n_steps):
+        _check(self.L.pd_batch_solve(self.h, int(n_steps), _stream()))
+        return self.U
+
+    def sync(self):
+        _check(self.L.pd_batch_sync(self.h, _stream()))
+
+
+BATCH_MENU = [(2, 1, 3), (2, 1, 5), (2, 1, 6), (2, 1, 7), (2, 2, 3), (1, 1, 5), (1, 1, 7),
+              (1, 2, 3)]  # (exchange, columns, rows) of the batch kernel's menu, by index

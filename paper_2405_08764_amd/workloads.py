@@ -209,6 +209,57 @@ def config3(n_r=64, n_theta=256, m=21, n_steps=2000, dt_macro=3.0e-5, n_t=492):
     return problem(g, fields, bc, src, timing(dt_macro, n_steps, n_t))
 
 
+def fit_time(prob, dt_macro_limit, dt_micro_limit, n_steps, frac=0.4, ratio=20.0):
+    """Time parameters from the explicit bounds: dt_macro at frac of the macro bound,
+    tau = dt_macro / ratio, n_t nano steps at no more than frac of the micro bound."""
+    dtm = frac * dt_macro_limit
+    n_t = max(1, int(math.ceil((dtm / ratio) / (frac * dt_micro_limit))))
+    return with_time(prob, dt_macro=dtm, n_steps=n_steps, n_t=n_t, ratio=ratio)
+
+
+def config4_instance(i, seed=MASTER_SEED + 4000, n_range=(17, 129), m_range=(9, 33),
+                     n_steps=1):
+    """Instance i of the mixed batch: square (tanh stretching beta ~ U[0, 3]) or annulus
+    (50/50), N x N macro nodes with N ~ U{n_range}, m x m micro points with m odd ~
+    U{m_range}, eps ~ log-U[1e-3, 1e-2], D and v from seeded Fourier modes (scalar D on
+    the annulus), reaction ~ U[0, 2], upwind convection, manufactured sources as the
+    square (e^-t sin pi x sin pi y) and annulus (e^-2t (r-1)(2-r) cos 2 theta + 0.1 sin
+    theta) configurations.  Time parameters are placeholders: fit them with fit_time
+    from the explicit bounds."""
+    rng = np.random.default_rng(seed + i)
+    annulus = bool(rng.random() < 0.5)
+    N = int(rng.integers(n_range[0], n_range[1] + 1))
+    m = int(rng.choice(np.arange(m_range[0], m_range[1] + 1, 2)))
+    beta = float(rng.uniform(0.0, 3.0))
+    react = float(rng.uniform(0.0, 2.0))
+    eps = float(10.0 ** rng.uniform(-3.0, -2.0))
+    if annulus:
+        k = fourier_field(rng, eps, 0.3 * eps)
+        fields = {"D11": k, "D22": copy.deepcopy(k), "v1": fourier_field(rng, 1.0, 0.3),
+                  "v2": fourier_field(rng, 0.5, 0.3), "f": field(c0=react)}
+        g = grid("annulus", N, N, m, m, box=(0.0, TWO_PI, 1.0, 2.0), periodic_xi=True,
+                 conv="upwind")
+        S1 = ("polar", 1.0, ("poly", -2.0, 3.0, -1.0, 0.0), ("cos", 2.0, 0.0))
+        S2 = ("polar", 0.1, ("poly", 1.0, 0.0, 0.0, 0.0), ("sin", 1.0, 0.0))
+        bc = [(texp(1.0, -2.0), S1), (const(1.0), S2)]
+        src = [(texp(1.0, -2.0), -2.0, S1), (const(1.0), 0.0, S2)]
+    else:
+        fields = {"D11": fourier_field(rng, eps, 0.3 * eps),
+                  "D22": fourier_field(rng, eps, 0.3 * eps),
+                  "v1": fourier_field(rng, 1.0, 0.3), "v2": fourier_field(rng, 0.5, 0.3),
+                  "f": field(c0=react)}
+        g = grid("tanh", N, N, m, m, gparam=beta, conv="upwind")
+        S = ("cart", 1.0, ("sin", math.pi, 0.0), ("sin", math.pi, 0.0))
+        bc = [(texp(1.0, -1.0), S)]
+        src = [(texp(1.0, -1.0), -1.0, S)]
+    return problem(g, fields, bc, src, timing(1.0, n_steps, 1))
+
+
+def config4(n_instances=512, **kw):
+    """The mixed batch: config4_instance(i) for i < n_instances."""
+    return [config4_instance(i, **kw) for i in range(n_instances)]
+
+
 def n_patches(g):
     nx = g["n_xi"] if g["periodic_xi"] else g["n_xi"] - 2
     return nx * (g["n_eta"] - 2)

@@ -110,3 +110,35 @@ def test_calls_without_workspace_report_state_error(pd):
     with pytest.raises(pd.PdError) as e:
         g.set_coefficients()
     assert e.value.status == -2
+
+
+def test_config4_generator_is_seeded_and_mixed():
+    """The mixed batch: deterministic per instance, both geometries, the stated ranges."""
+    from paper_2405_08764_amd import workloads as W
+    a = W.config4(64)
+    b = W.config4(64)
+    assert a == b
+    geos = {p["grid"]["geometry"] for p in a}
+    assert geos == {"tanh", "annulus"}
+    for p in a:
+        g = p["grid"]
+        assert 17 <= g["n_xi"] <= 129 and g["n_xi"] == g["n_eta"]
+        assert 9 <= g["m_xi"] <= 33 and g["m_xi"] % 2 == 1
+        assert abs(g["h_xi"] / ((g["xi1"] - g["xi0"]) / (g["n_xi"] - (0 if g["periodic_xi"] else 1))) - 0.2) < 1e-12
+        assert 0.0 <= p["fields"]["f"]["c0"] <= 2.0
+        eps = p["fields"]["D11"]["c0"]
+        assert 1e-3 <= eps <= 1e-2
+    assert W.config4_instance(3) != W.config4_instance(4)
+
+
+def test_batch_create_rejects_members_without_coefficients(pd):
+    """pd_batch_create validates its members on the host (no device needed)."""
+    import ctypes as C
+    from paper_2405_08764_amd import workloads as W
+    g = pd.Grid(W.config1(), coefficients=False)
+    arr = (pd.BatchMember * 1)()
+    arr[0] = pd.BatchMember(g.h.value, 0x1000, 0.0, 0.01, 1e-5, 4)
+    h = C.c_void_p()
+    st = pd.lib().pd_batch_create(arr, 1, C.byref(h))
+    assert st == -2  # PD_ESTATE: no workspace / coefficients
+    assert pd.lib().pd_batch_create(arr, 0, C.byref(h)) == -1

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6e12, "f32": 157.3e12}  # MI355X vector ALU FLOP/s (dense, published)
-KERNEL_NAME = {1: "k_burst", 2: "k_burst_x"}  # by neighbour exchange (LDS, in-wave)
+KERNEL_NAME = {1: "k_burst", 2: "k_burst_x", 3: "k_burst_h"}  # by exchange: LDS, in-wave, hybrid
 
 
 def workload(name):
@@ -35,7 +35,8 @@ def workload(name):
 
 
 BURST_SOURCES = ["pd_burst.inc", "pd_internal.h", "pd_burst_x_f64.hip", "pd_burst_x_f32.hip",
-                 "pd_burst_lds_f64.hip", "pd_burst_lds_f32.hip"]
+                 "pd_burst_lds_f64.hip", "pd_burst_lds_f32.hip", "pd_burst_h_f64.hip",
+                 "pd_burst_h_f32.hip"]
 
 
 def burst_source_hash():
@@ -138,13 +139,82 @@ def cpu_baseline(prob, budget_s, steps_cap):
             "macro_steps_per_s": done / el}
 
 
+def bench_batch(args):
+    """The mixed batch: every instance advances one macro step per persistent launch."""
+    import torch
+
+    from paper_2405_08764_amd import pd
+    from paper_2405_08764_amd import workloads as W
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    t_setup = time.perf_counter()
+    with torch.cuda.stream(stream):
+        grids = []
+        for p in W.config4(args.instances):
+            g = pd.Grid(p)
+            info = g.query()
+            g.prob = W.fit_time(p, info.dt_macro_limit, info.dt_micro_limit, args.steps)
+            grids.append(g)
+        B = pd.Batch(grids)
+        untuned = B.query()
+        tuned_ms = B.autotune(reps=2)
+        binfo = B.query()
+        print(f"[bench] batch of {len(grids)}: {binfo.n_items} items, {binfo.blocks} blocks, "
+              f"setup {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
+        B.solve(max(args.warmup // 8, 2))
+        B.sync()
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        B.solve(args.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - s
+        B.sync()
+    per_step = binfo.updates_per_step
+    shapes = {}
+    for i in range(len(grids)):
+        sh, ppb = B.shape(i)
+        key = f"m={grids[i].mx}"
+        shapes.setdefault(key, set()).add(f"{pd.BATCH_MENU[sh]}x{ppb}")
+    achieved = 20 * per_step / (tuned_ms * 1e-3)
+    peak = PEAK["f64"]
+    P = sum(g.P for g in grids)
+    pts = sum(g.P * g.mx * g.me for g in grids)
+    n_ts = [g.prob["time"]["n_t"] for g in grids]
+    out = {
+        "metric": "patch-point updates/s (and macro steps/s) of the batched plain scheme",
+        "value": per_step * args.steps / el,
+        "unit": "patch-point updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": max(args.warmup // 8, 2),
+        "ms_per_step": el / args.steps * 1e3,
+        "macro_steps_per_s": args.steps / el,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded analytic coefficients, no dataset)",
+        "config": {"workload": f"config4: {len(grids)} mixed instances (tanh squares and "
+                               "annuli, N 17..129, m 9..33, Fourier D and v, eps "
+                               "1e-3..1e-2, reaction 0..2), one persistent launch per step",
+                   "patches": P, "micro_points": pts, "updates_per_step": per_step,
+                   "n_t_range": [min(n_ts), max(n_ts)], "items": binfo.n_items,
+                   "blocks": binfo.blocks, "lds_bytes": binfo.lds_bytes,
+                   "untuned_items": untuned.n_items,
+                   "shapes": {k: sorted(v) for k, v in sorted(shapes.items())}},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_batch (persistent, one batch macro step)",
+                     "kernel_ms": tuned_ms, "flops_per_update": 20},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config3"])
+    ap.add_argument("--workload", default="config2",
+                    choices=["config1", "config2", "config3", "config4"])
+    ap.add_argument("--instances", type=int, default=512,
+                    help="config4: number of mixed instances in the batch")
     ap.add_argument("--kernel-reps", type=int, default=64)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -163,7 +233,7 @@ def main():
     ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
     if args.pmc_summary:
-        kernel = "k_burst_x" if args.pmc_shape.startswith("2,") else "k_burst"
+        kernel = KERNEL_NAME[int(args.pmc_shape.split(",")[0])]
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], kernel + "<",
                     args.calibrate_copy or 256,
                     traffic_file(kernel, args.workload, args.precision), args.pmc_command,
@@ -180,6 +250,8 @@ def main():
     from paper_2405_08764_amd import pd
     from paper_2405_08764_amd import workloads as W
 
+    if args.workload == "config4":
+        return bench_batch(args)
     prob, desc = workload(args.workload)
     t = prob["time"]
     torch.cuda.set_device(0)
@@ -269,7 +341,7 @@ def main():
                               "cols_per_lane": info.cols_per_lane,
                               "patches_per_block": info.patches_per_block,
                               "block_threads": info.block_threads,
-                              "exchange": "in-wave" if info.exchange == 2 else "lds",
+                              "exchange": {1: "lds", 2: "in-wave", 3: "hybrid"}[info.exchange],
                               "autotuned": bool(info.tuned), "tuned_ms": tuned_ms}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,

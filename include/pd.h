@@ -75,6 +75,8 @@ typedef struct {
   int32_t c0mode;                 /* PD_C0_*                                            */
   int32_t precision;              /* PD_F64 / PD_F32                                    */
   int32_t device;                 /* HIP device ordinal                                 */
+  int32_t max_sources;            /* source terms the workspace holds planes for        */
+                                  /* (0 = PD_MAXTERM); pd_set_coefficients checks it    */
 } pd_grid_desc;
 
 /* Scalar field F(x, y) = c0 + cx x + cy y + sum amp cos(kx x + ky y + ph)
@@ -129,7 +131,8 @@ typedef struct {
   int32_t n_time_sources;    /* source terms with a non-constant time factor           */
   int32_t rows_per_lane, patches_per_block, block_threads; /* current launch shape     */
   int32_t cols_per_lane;
-  int32_t exchange;          /* 1: neighbours through LDS, 2: inside one wave (DPP)   */
+  int32_t exchange;          /* 1: neighbours through LDS, 2: inside one wave (DPP),  */
+                             /* 3: DPP inside each wave, band edges through LDS        */
   int32_t tuned;             /* 1 once pd_autotune chose the launch shape               */
   double tuned_ms;           /* its measured time per fused step (ms), else 0           */
 } pd_info;
@@ -205,7 +208,7 @@ pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
 
 /* Options: PD_OPT_ALLOW_UNSTABLE (0/1) skips the stability guard; PD_OPT_ROWS_PER_LANE,
  * PD_OPT_COLS_PER_LANE (1..3), PD_OPT_PATCHES_PER_BLOCK, PD_OPT_BLOCK_THREADS (upper bound,
- * 64..256) and PD_OPT_EXCHANGE (1 LDS, 2 in-wave) set the fused burst's launch shape
+ * 64..256) and PD_OPT_EXCHANGE (1 LDS, 2 in-wave, 3 hybrid) set the fused burst's launch shape
  * (0 = automatic).  Results do not depend on the launch shape (bitwise). */
 #define PD_OPT_ALLOW_UNSTABLE 1
 #define PD_OPT_ROWS_PER_LANE 2

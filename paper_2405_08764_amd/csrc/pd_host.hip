@@ -25,6 +25,8 @@ PD_DECL(lds_f64)
 PD_DECL(lds_f32)
 PD_DECL(x_f64)
 PD_DECL(x_f32)
+PD_DECL(h_f64)
+PD_DECL(h_f32)
 #undef PD_DECL
 
 hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const BurstArgs& a,
@@ -33,6 +35,9 @@ hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const Bu
   if (xch == XCH_LANES)
     return precision == PD_F32 ? launch_burst_x_f32(R, C, mode, a, blocks, threads, lds, s)
                                : launch_burst_x_f64(R, C, mode, a, blocks, threads, lds, s);
+  if (xch == XCH_HYBRID)
+    return precision == PD_F32 ? launch_burst_h_f32(R, C, mode, a, blocks, threads, lds, s)
+                               : launch_burst_h_f64(R, C, mode, a, blocks, threads, lds, s);
   return precision == PD_F32 ? launch_burst_lds_f32(R, C, mode, a, blocks, threads, lds, s)
                              : launch_burst_lds_f64(R, C, mode, a, blocks, threads, lds, s);
 }
@@ -40,7 +45,8 @@ hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const Bu
 bool burst_shape_supported(int R, int C) {
   if (C == 1) return R == 3 || R == 4 || R == 5 || R == 6 || R == 7 || R == 8 || R == 9 || R == 11;
   if (C == 2) return R >= 2 && R <= 6;
-  if (C == 3) return R == 2 || R == 3;
+  if (C == 3) return R >= 2 && R <= 4;
+  if (C == 4) return R == 2 || R == 3;
   return false;
 }
 }  // namespace pdk
@@ -115,6 +121,7 @@ struct pd_grid_s {
   bool coeffs_set = false;
   pd_coeff_desc cd{};
   int n_src = 0;
+  int max_src = PD_MAXTERM;  // source planes the workspace holds
   SrcInfo src{};
   double lim_micro = 0.0, lim_macro = 0.0;
   // options
@@ -138,6 +145,12 @@ struct pd_grid_s {
   // autotuner result
   int tuned = 0;
   double tuned_ms = 0.0;
+  // what the time-factor table holds (single-step layout), so repeated steps from the
+  // same time on the same stream skip recomputing it
+  bool tt_ok = false;
+  double tt_t = 0.0, tt_dt = 0.0;
+  int tt_nt = 0;
+  hipStream_t tt_s = nullptr;
 
   double* coef() { return reinterpret_cast<double*>(ws + off_coef); }
   int* dpmap() { return reinterpret_cast<int*>(ws + off_pmap); }
@@ -177,10 +190,10 @@ bool next_shape(pd_grid g, int xch_only, bool split, std::vector<Shape>& out) {
   const int mx = g->g.m_xi, me = g->g.m_eta;
   const int candR[] = {2, 3, 4, 5, 6, 7, 8, 9, 11};
   out.clear();
-  for (int xch = XCH_LDS; xch <= XCH_LANES; ++xch) {
+  for (int xch = XCH_LDS; xch <= XCH_HYBRID; ++xch) {
     if (split && xch != XCH_LDS) continue;
     if (xch_only && xch != xch_only) continue;
-    for (int C = 1; C <= 3; ++C) {
+    for (int C = 1; C <= 4; ++C) {
       if (g->opt_C && C != g->opt_C) continue;
       for (int R : candR) {
         if (!burst_shape_supported(R, C) || (g->opt_R && R != g->opt_R)) continue;
@@ -188,16 +201,26 @@ bool next_shape(pd_grid g, int xch_only, bool split, std::vector<Shape>& out) {
         const int LP = Lb * B;
         for (int cap = 64; cap <= 256; cap += 64) {
           if (xch == XCH_LANES && cap != 64) break;
+          if (xch == XCH_HYBRID && cap == 64) continue;  // one wave: the in-wave kernel
           if (g->opt_threads && cap > g->opt_threads) break;
-          if (LP > cap) continue;
-          int ppb = cap / LP;
-          if (g->opt_ppb) ppb = g->opt_ppb < ppb ? g->opt_ppb : ppb;
-          const int threads = ((ppb * LP + 63) / 64) * 64;
+          int ppb, threads;
+          if (xch == XCH_HYBRID) {  // whole bands per wave; patches take B bands
+            if (Lb > 64) continue;
+            ppb = (cap / 64) * (64 / Lb) / B;
+            if (ppb < 1) continue;
+            if (g->opt_ppb) ppb = g->opt_ppb < ppb ? g->opt_ppb : ppb;
+            threads = cap;
+          } else {
+            if (LP > cap) continue;
+            ppb = cap / LP;
+            if (g->opt_ppb) ppb = g->opt_ppb < ppb ? g->opt_ppb : ppb;
+            threads = ((ppb * LP + 63) / 64) * 64;
+          }
           if (burst_lds_bytes(g->d.precision, R, C, xch, threads, ppb, mx, me, g->src.ns) > 65536)
             continue;
           const double eff = (double)ppb * mx * me / ((double)threads * R * C);
-          const double score = eff * (xch == XCH_LANES ? 1.5 : 1.0) + 1e-3 * (C - 1) + 1e-4 * R -
-                               1e-5 * threads;
+          const double w = xch == XCH_LANES ? 1.5 : (xch == XCH_HYBRID ? 1.4 : 1.0);
+          const double score = eff * w + 1e-3 * (C - 1) + 1e-4 * R - 1e-5 * threads;
           out.push_back({R, C, xch, ppb, threads, score});
         }
       }
@@ -316,6 +339,21 @@ pd_status guard_macro(pd_grid g, double dtm, double dt, int n_t) {
   return PD_OK;
 }
 
+hipError_t ensure_time_table(pd_grid g, double t_n, double dt, int n_t, hipStream_t s) {
+  if (g->tt_ok && g->tt_t == t_n && g->tt_dt == dt && g->tt_nt == n_t && g->tt_s == s)
+    return hipSuccess;
+  g->tt_ok = false;
+  const hipError_t e = launch_time_table(g->src, t_n, dt, n_t, g->ttab(), s);
+  if (e == hipSuccess) {
+    g->tt_ok = true;
+    g->tt_t = t_n;
+    g->tt_dt = dt;
+    g->tt_nt = n_t;
+    g->tt_s = s;
+  }
+  return e;
+}
+
 BurstArgs base_args(pd_grid g, double t_n, double dt, int n_t) {
   BurstArgs a{};
   a.g = g->g;
@@ -371,9 +409,12 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
     default: return fail(PD_EINVAL, "bad geometry");
   }
   if (D.device < 0) return fail(PD_EINVAL, "negative device ordinal");
+  if (D.max_sources < 0 || D.max_sources > PD_MAXTERM)
+    return fail(PD_EINVAL, "max_sources must be in 0..PD_MAXTERM");
 
   pd_grid g = new pd_grid_s();
   g->d = D;
+  g->max_src = D.max_sources > 0 ? D.max_sources : PD_MAXTERM;
   Geo& G = g->g;
   G.geometry = D.geometry;
   G.gparam = D.gparam;
@@ -435,7 +476,7 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
   // Workspace layout.
   size_t o = 0;
   const size_t npts = (size_t)G.P * mx * me;
-  g->off_coef = o; o = align256(o + (5 + PD_MAXTERM) * npts * sizeof(double));
+  g->off_coef = o; o = align256(o + (5 + g->max_src) * npts * sizeof(double));
   g->off_pmap = o; o = align256(o + g->pmap.size() * sizeof(int32_t));
   g->off_tab = o; o = align256(o + g->tab.size() * sizeof(double));
   g->off_desc = o; o = align256(o + sizeof(pd_coeff_desc));
@@ -514,6 +555,8 @@ pd_status pd_set_coefficients(pd_grid g, const pd_coeff_desc* c, void* stream) {
     return st;
   if (ann && std::memcmp(&c->D11, &c->D22, sizeof(pd_field)) != 0)
     return fail(PD_EINVAL, "the annulus takes a scalar diffusion coefficient (D11 == D22)");
+  if (c->n_src > g->max_src)
+    return fail(PD_EINVAL, "more source terms than the grid was created for (max_sources)");
   if (c->n_bc < 0 || c->n_bc > PD_MAXTERM || c->n_src < 0 || c->n_src > PD_MAXTERM)
     return fail(PD_EINVAL, "term count out of range");
   SrcInfo si{};
@@ -552,6 +595,7 @@ pd_status pd_set_coefficients(pd_grid g, const pd_coeff_desc* c, void* stream) {
   g->lim_micro = lim[0];
   g->lim_macro = lim[1];
   g->coeffs_set = true;
+  g->tt_ok = false;
   choose_shape(g);
   return PD_OK;
 }
@@ -586,7 +630,7 @@ pd_status pd_micro_burst(pd_grid g, double* state, const double* edge, double t_
   a.state = state;
   a.edge = edge;
   a.ppb = g->sppb;
-  HIPCHK(launch_time_table(g->src, t_n, dt, n_t, g->ttab(), static_cast<hipStream_t>(stream)));
+  HIPCHK(ensure_time_table(g, t_n, dt, n_t, static_cast<hipStream_t>(stream)));
   HIPCHK(launch_burst(g->d.precision, g->sR, g->sC, XCH_LDS, MODE_SPLIT, a, g->sblocks,
                       g->sthreads, g->slds, static_cast<hipStream_t>(stream)));
   return PD_OK;
@@ -620,7 +664,7 @@ pd_status pd_macro_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
     a.Unew = U_np1;
     a.dt_macro = dt_macro;
     a.tau = tau;
-    HIPCHK(launch_time_table(g->src, t_n, dt, n_t, g->ttab(), s));
+    HIPCHK(ensure_time_table(g, t_n, dt, n_t, s));
     HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds, s));
   }
   HIPCHK(launch_boundary(g->g, g->ddesc(), U_np1, t_n + dt_macro, s));
@@ -639,7 +683,7 @@ pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
   a.Unew = U_np1;
   a.dt_macro = dt_macro;
   a.tau = n_t * dt;
-  HIPCHK(launch_time_table(g->src, t_n, dt, n_t, g->ttab(), static_cast<hipStream_t>(stream)));
+  HIPCHK(ensure_time_table(g, t_n, dt, n_t, static_cast<hipStream_t>(stream)));
   HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_FUSED, a, g->blocks, g->threads, g->lds,
                       static_cast<hipStream_t>(stream)));
   return PD_OK;
@@ -689,6 +733,7 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     HIPCHK(hipEventRecord(g->ev_in, s));
     HIPCHK(hipStreamWaitEvent(w, g->ev_in, 0));
   }
+  g->tt_ok = false;  // k_replay rewrites the time-factor table
   HIPCHK(launch_clock_init(g->clock(), t0, dt_macro, U, g->V(), w));
   auto steps = [&](int count) -> hipError_t {
     hipError_t e = launch_replay(g->g, g->src, g->ddesc(), g->clock(), count, n_t, dt,
@@ -773,7 +818,7 @@ pd_status pd_autotune(pd_grid g, const double* U, double t_n, double dt_macro, d
   const Shape keep{g->R, g->C, g->xch, g->ppb, g->threads, 0.0};
   double best = 1e300;
   Shape bs = keep;
-  hipError_t e = launch_time_table(g->src, t_n, dt, n_t, g->ttab(), s);
+  hipError_t e = ensure_time_table(g, t_n, dt, n_t, s);
   for (size_t q = 0; q < cand.size() && e == hipSuccess; ++q) {
     apply_shape(g, cand[q]);
     BurstArgs a = base_args(g, t_n, dt, n_t);
@@ -786,13 +831,26 @@ pd_status pd_autotune(pd_grid g, const double* U, double t_n, double dt_macro, d
                           g->threads, g->lds, s);
     };
     if ((e = launch()) != hipSuccess) break;  // warm-up (code load, caches)
-    if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
-    if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess) break;
-    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-    float ms = 0.f;
-    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-    const double per = (double)ms / reps;
+    // best of three trials of `reps` launches each (the first also sizes later trials)
+    double best_trial = 1e300;
+    int n = reps;
+    for (int trial = 0; trial < 3 && e == hipSuccess; ++trial) {
+      if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+      for (int r = 0; r < n && e == hipSuccess; ++r) e = launch();
+      if (e != hipSuccess || (e = hipEventRecord(e1, s)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+      float f = 0.f;
+      if ((e = hipEventElapsedTime(&f, e0, e1)) != hipSuccess) break;
+      const double per_launch = (double)f / n;
+      if (per_launch < best_trial) best_trial = per_launch;
+      if (trial == 0 && per_launch * n < 0.5) {  // trials of at least ~0.5 ms
+        const int want = (int)(0.5 / (per_launch > 1e-6 ? per_launch : 1e-6)) + 1;
+        n = want > 64 ? 64 : want;
+      }
+    }
+    if (e != hipSuccess) break;
+    float ms = (float)best_trial;
+    const double per = (double)ms;
     if (per < best) {
       best = per;
       bs = cand[q];
@@ -865,11 +923,12 @@ pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
       g->opt_R = (int)value;
       break;
     case PD_OPT_COLS_PER_LANE:
-      if (value < 0 || value > 3) return fail(PD_EINVAL, "columns per lane must be 1, 2 or 3");
+      if (value < 0 || value > 4) return fail(PD_EINVAL, "columns per lane must be 1 to 4");
       g->opt_C = (int)value;
       break;
     case PD_OPT_EXCHANGE:
-      if (value < 0 || value > 2) return fail(PD_EINVAL, "exchange must be 0, 1 (LDS) or 2 (lanes)");
+      if (value < 0 || value > 3)
+        return fail(PD_EINVAL, "exchange must be 0, 1 (LDS), 2 (in-wave) or 3 (hybrid)");
       g->opt_xch = (int)value;
       break;
     case PD_OPT_PATCHES_PER_BLOCK:

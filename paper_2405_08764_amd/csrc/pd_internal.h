@@ -81,20 +81,16 @@ __host__ __device__ inline int boundary_count(const Geo& g) {
 }
 __host__ __device__ inline void boundary_node(const Geo& g, int q, int& i, int& j) {
   const int nb_rows = 2 * g.n_xi;
-  if (q < nb_rows) {
-    i = q % g.n_xi;
-    j = q < g.n_xi ? 0 : g.n_eta - 1;
-  } else {
-    const int r = q - nb_rows;
-    j = 1 + r / 2;
-    i = (r & 1) ? g.n_xi - 1 : 0;
-  }
+  const int r = q - nb_rows;
+  i = q < nb_rows ? q % g.n_xi : ((r & 1) ? g.n_xi - 1 : 0);
+  j = q < nb_rows ? (q < g.n_xi ? 0 : g.n_eta - 1) : 1 + r / 2;
 }
 
 enum { MODE_SPLIT = 0, MODE_FUSED = 1 };
-// Neighbour exchange of the burst: through LDS (any block size) or inside one wave
-// (DPP wave shifts and ds_bpermute, single-wave blocks).
-enum { XCH_LDS = 1, XCH_LANES = 2 };
+// Neighbour exchange of the burst: through LDS (any block size), inside one wave (DPP
+// wave shifts and ds_bpermute, single-wave blocks), or hybrid (DPP inside each wave, band
+// edges through LDS, blocks of several waves).
+enum { XCH_LDS = 1, XCH_LANES = 2, XCH_HYBRID = 3 };
 
 struct BurstArgs {
   Geo g;
@@ -154,18 +150,24 @@ bool burst_shape_supported(int R, int C);
 
 // Dynamic LDS bytes of a burst launch: the lane-major exchange tiles (double-buffered,
 // guard of lanes-per-band + 1 words on both sides) or the FP64 lifted tile of the
-// prologue, whichever is larger, then the time-factor chunk and the restriction rows.
+// prologue, whichever is larger, then the time-factor chunk, the restriction rows and a
+// copy of the stencil tables.
 __host__ __device__ inline size_t burst_lds_bytes(int precision, int R, int C, int xch,
                                                   int threads, int ppb, int mx, int me,
                                                   int ns) {
   const size_t rs = precision == PD_F32 ? 4 : 8;
   const int Lb = (mx + C - 1) / C;
-  const size_t nbuf = xch == XCH_LANES ? 1 : 2;
-  const size_t exch = nbuf * R * C * (size_t)(threads + 2 * (Lb + 1)) * rs;
+  const size_t nbuf = xch == XCH_LDS ? 2 : 1;
+  size_t exch = nbuf * R * C * (size_t)(threads + 2 * (Lb + 1)) * rs;
+  if (xch == XCH_HYBRID) {  // band-edge planes: 2 buffers x (top, bottom) x (bands + 2)
+    const size_t edges = (size_t)4 * ((threads / 64) * (64 / Lb) + 2) * C * Lb * rs;
+    if (edges > exch) exch = edges;
+  }
   const size_t lift = (size_t)ppb * (mx + 2) * (me + 2) * 8;
   const size_t region = ((exch > lift ? exch : lift) + 15) & ~size_t(15);
   const int TCH = 256;
-  return region + (size_t)(ns > 0 ? ns : 1) * TCH * 8 + (size_t)ppb * me * 8 + 64;
+  return region + (size_t)(ns > 0 ? ns : 1) * TCH * 8 + (size_t)ppb * me * 8 +
+         (size_t)tab_off(mx, me).size * 8 + 64;
 }
 
 // ---------------------------------------------------------------- batched bursts

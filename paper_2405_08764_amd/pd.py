@@ -41,7 +41,7 @@ class GridDesc(C.Structure):
                 ("n_xi", C.c_int32), ("n_eta", C.c_int32), ("periodic_xi", C.c_int32),
                 ("h_xi", C.c_double), ("h_eta", C.c_double), ("m_xi", C.c_int32),
                 ("m_eta", C.c_int32), ("conv", C.c_int32), ("c0mode", C.c_int32),
-                ("precision", C.c_int32), ("device", C.c_int32)]
+                ("precision", C.c_int32), ("device", C.c_int32), ("max_sources", C.c_int32)]
 
 
 class Field(C.Structure):
@@ -209,7 +209,7 @@ def _tfun(t):
     return T
 
 
-def grid_desc(g, precision="f64", device=0):
+def grid_desc(g, precision="f64", device=0, max_sources=0):
     D = GridDesc()
     D.geometry = GEOM[g["geometry"]]
     D.gparam = g["gparam"]
@@ -222,6 +222,7 @@ def grid_desc(g, precision="f64", device=0):
     D.c0mode = C0MODE[g["c0"]]
     D.precision = PREC[precision]
     D.device = device
+    D.max_sources = max_sources
     return D
 
 
@@ -250,7 +251,8 @@ class Grid:
         self.L = lib()
         self.device = torch.device("cuda", device) if torch.cuda.is_available() else None
         self.h = C.c_void_p()
-        _check(self.L.pd_create_grid(C.byref(grid_desc(prob["grid"], precision, device)),
+        desc = grid_desc(prob["grid"], precision, device, max_sources=max(1, len(prob["src"])))
+        _check(self.L.pd_create_grid(C.byref(desc),
                                      C.byref(self.h)))
         self.info = self.query()
         self.P = self.info.n_patches

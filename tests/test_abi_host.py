@@ -78,8 +78,13 @@ def test_info_and_workspace_size(pd):
     g = _grid(pd, prob)
     I = g.query()
     assert I.n_patches == 15 * 15 and I.n_points == 225 * 289
-    assert I.workspace_bytes >= (5 + 4) * I.n_points * 8
+    # planes for alpha, gamma, nu, omega, phi and the problem's one source term
+    assert I.workspace_bytes >= (5 + 1) * I.n_points * 8
+    assert I.workspace_bytes < (5 + 2) * I.n_points * 8 + (1 << 21)  # + tables, time factors
     assert I.rows_per_lane > 0 and I.block_threads % 64 == 0 and I.block_threads <= 256
+    d = pd.grid_desc(prob["grid"], max_sources=pd.MAXTERM + 1)
+    h = C.c_void_p()
+    assert pd.lib().pd_create_grid(C.byref(d), C.byref(h)) == -1
 
 
 @pytest.mark.parametrize("field,value", [("h_xi", 1.0), ("m_xi", 2), ("m_eta", 65),

@@ -174,7 +174,7 @@ def test_solve_matches_oracle(pd, oracle_mod, problems, case, precision):
     assert err <= (1e-11 if precision == "f64" else 5e-6), err
 
 
-@pytest.mark.parametrize("xch", [1, 2])
+@pytest.mark.parametrize("xch", [1, 2, 3])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_fused_step_equals_split_path(pd, oracle_mod, problems, precision, xch):
     """The fused kernel (either neighbour exchange) and the stage-by-stage calls compute
@@ -246,7 +246,7 @@ def test_bitwise_determinism_across_runs_and_launch_shapes(pd, problems):
     again = g.solve().cpu().numpy()
     assert ref.tobytes() == again.tobytes()
     seen = set()
-    for xch in (1, 2):
+    for xch in (1, 2, 3):
         for C in (1, 2, 3):
             for R in (2, 3, 4, 5, 6, 7, 8, 9, 11):
                 for ppb in (1, 2, 0):
@@ -264,7 +264,7 @@ def test_bitwise_determinism_across_runs_and_launch_shapes(pd, problems):
                     seen.add(key)
                     out = g.solve().cpu().numpy()
                     assert out.tobytes() == ref.tobytes(), key
-    assert {k[0] for k in seen} == {1, 2}, seen
+    assert {k[0] for k in seen} == {1, 2, 3}, seen
 
 
 @pytest.mark.parametrize("name", ["config1", "sec412_sine", "ragged_13x7"])

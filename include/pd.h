@@ -285,6 +285,59 @@ pd_status pd_batch_solve(pd_batch b, int32_t n_steps, void* stream);
 /* Synchronise and report PD_ENONFINITE if any member's kernels saw a non-finite value. */
 pd_status pd_batch_sync(pd_batch b, void* stream);
 
+/* ---------------------------------------------------------------------- learned closure
+ * A small network that stands in for a patch's micro-burst (not in the paper: an addition
+ * whose targets the plain scheme produces and which the plain scheme checks).  For the
+ * patch at macro node (i, j) it predicts F = (R(u(tau)) - U)/tau (eq. Time_Derivative) as
+ *   F_hat = F0 + s y_hat,
+ * F0 the macro finite-difference operator at the node with the patch-centre coefficients,
+ * s = kappa sigma + 1e-3 (|g| + |phi U|) (kappa: sum of the rates alpha/Dxi^2,
+ * gamma/Deta^2, |nu|/Dxi, |omega|/Deta, |phi|; sigma: RMS of the 24 stencil differences),
+ * and y_hat the network output on 33 inputs: the 24 differences of the 5x5 stencil / sigma
+ * (row-major, centre skipped; indices wrap on a periodic axis, clamp otherwise),
+ * U/(|U| + sigma), the five rates / kappa, q/(1+|q|) with q = g/(kappa (|U| + sigma)), and
+ * the scale factors h1, h2 at the node; standardised per input.  Network 33 -> 128 -> 128 ->
+ * 1 with GELU(x) = x Phi(x); parameters as one FP32 vector W1 [33][128] (input-major), b1,
+ * W2 [128][128], b2, w3 [128], b3 (20993 values).  Training runs in FP32 (mean squared
+ * error, Adam with beta1 0.9, beta2 0.999, eps 1e-8); inference rounds inputs, weights and
+ * first-layer activations to bfloat16 and accumulates in FP32 on MFMA.  All pointers are
+ * device pointers unless named host_. */
+typedef struct pd_closure_s* pd_closure;
+/* max_batch: rows per training step and per inference chunk (64..4194304). */
+pd_status pd_closure_create(int32_t device, int32_t max_batch, pd_closure* out);
+pd_status pd_closure_destroy(pd_closure c);
+pd_status pd_closure_query(pd_closure c, size_t* workspace_bytes, int32_t* n_params);
+/* Zeroes the workspace; parameters and standardisation must then be set. */
+pd_status pd_closure_bind_workspace(pd_closure c, void* dev, size_t bytes);
+/* Host vectors of 20993 FP32 values; setting resets the optimiser state. */
+pd_status pd_closure_set_params(pd_closure c, const float* host_params);
+pd_status pd_closure_get_params(pd_closure c, float* host_params);
+/* Per-input mean and standard deviation (33 each, host), or fitted on the device to rows
+ * X [n][33] of raw inputs. */
+pd_status pd_closure_set_standardisation(pd_closure c, const float* host_mu, const float* host_sd);
+pd_status pd_closure_get_standardisation(pd_closure c, float* host_mu, float* host_sd);
+pd_status pd_closure_fit_standardisation(pd_closure c, const float* X, int64_t n, void* stream);
+/* Raw inputs X [P][33] (FP32), F0 [P] and s [P] (FP64, may be NULL) of every patch of a
+ * grid for the macro field U at time t_n. */
+pd_status pd_closure_features(pd_grid g, const double* U, double t_n, float* X, double* F0,
+                              double* s, void* stream);
+/* Mean-squared-error loss (FP32 [1]) and gradients (FP32 [20993], layout of the
+ * parameters) on n <= max_batch rows of raw inputs X and targets y. */
+pd_status pd_closure_gradients(pd_closure c, const float* X, const float* y, int32_t n,
+                               float* grad, float* loss, void* stream);
+/* `epochs` passes over n rows in minibatches of `batch` rows (a seeded affine shuffle per
+ * epoch, n / batch full batches), one Adam step each; host_losses (may be NULL) receives
+ * the mean minibatch loss of each epoch (then the call synchronises per epoch). */
+pd_status pd_closure_train(pd_closure c, const float* X, const float* y, int64_t n,
+                           int32_t batch, int32_t epochs, float lr, uint32_t seed,
+                           float* host_losses, void* stream);
+/* Network outputs y_hat [n] (FP32) for raw inputs X [n][33], bfloat16 MFMA path. */
+pd_status pd_closure_infer(pd_closure c, const float* X, float* out, int64_t n, void* stream);
+/* The closure macro step of every patch node of a grid: U_np1 = U_n + dt_macro F_hat
+ * (boundary nodes untouched; F_hat [P] FP64 stored when non-NULL).  U_n, U_np1 distinct. */
+pd_status pd_closure_patch_step(pd_closure c, pd_grid g, const double* U_n, double* U_np1,
+                                double t_n, double dt_macro, double* F_hat, void* stream);
+
 const char* pd_last_error(void);
 
 #ifdef __cplusplus

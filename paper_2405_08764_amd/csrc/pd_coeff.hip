@@ -382,6 +382,36 @@ __global__ void k_batch_replay(const BurstArgs* __restrict__ inst,
   }
 }
 
+// Static inputs of the learned closure per patch: the coefficients at the patch centre
+// as rates on the macro spacing (alpha/Dxi^2, gamma/Deta^2, nu/Dxi, omega/Deta), phi, the
+// scale factors h1, h2 at the node, and the source's spatial parts at the centre.
+__global__ void k_closure_static(Geo g, SrcInfo src, const int* __restrict__ pmap,
+                                 const double* __restrict__ coef, long long plane,
+                                 double* __restrict__ st) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  const int i = pmap[11 * p], j = pmap[11 * p + 1];
+  const long long at =
+      (long long)p * g.m_xi * g.m_eta + (long long)(g.m_eta / 2) * g.m_xi + g.m_xi / 2;
+  Metric m;
+  metric_at(g, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, m);
+  double* o = st + (long long)p * CL_NST;
+  o[0] = i;
+  o[1] = j;
+  o[2] = coef[at] / (g.Dxi * g.Dxi);
+  o[3] = coef[plane + at] / (g.Deta * g.Deta);
+  o[4] = coef[2 * plane + at] / g.Dxi;
+  o[5] = coef[3 * plane + at] / g.Deta;
+  o[6] = coef[4 * plane + at];
+  o[7] = sqrt(m.x_s * m.x_s + m.y_s * m.y_s);
+  o[8] = sqrt(m.x_e * m.x_e + m.y_e * m.y_e);
+  double gc = 0.0;
+  for (int c = 0; c < src.nconst; ++c) gc += src.ca[c] * coef[src.plane_c[c] * plane + at];
+  o[9] = gc;
+  o[10] = src.ns > 0 ? coef[src.plane_t[0] * plane + at] : 0.0;
+  o[11] = src.ns > 1 ? coef[src.plane_t[1] * plane + at] : 0.0;
+}
+
 __global__ void k_initial(Geo g, const pd_coeff_desc* __restrict__ desc, double* U, double t) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.n_xi * g.n_eta) return;
@@ -425,6 +455,14 @@ hipError_t launch_limits(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
 hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_boundary, dim3(1), dim3(256), 0, s, g, dev_desc, U, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_closure_static(const Geo& g, const SrcInfo& src, const int* pmap,
+                                 const double* coef, long long plane, double* st,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_closure_static, dim3((g.P + 255) / 256), dim3(256), 0, s, g, src, pmap,
+                     coef, plane, st);
   return hipGetLastError();
 }
 

@@ -116,7 +116,9 @@ struct pd_grid_s {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_coef = 0, off_pmap = 0, off_tab = 0, off_desc = 0, off_V = 0, off_flag = 0,
-         off_clock = 0, off_part = 0, off_lim = 0, off_ttab = 0, off_bval = 0, need = 0;
+         off_clock = 0, off_part = 0, off_lim = 0, off_ttab = 0, off_bval = 0, off_cst = 0,
+         need = 0;
+  bool cst_ok = false;  // static closure data computed for the current coefficients
   // coefficients
   bool coeffs_set = false;
   pd_coeff_desc cd{};
@@ -163,6 +165,7 @@ struct pd_grid_s {
   double* lim() { return reinterpret_cast<double*>(ws + off_lim); }
   double* ttab() { return reinterpret_cast<double*>(ws + off_ttab); }
   double* bvals() { return reinterpret_cast<double*>(ws + off_bval); }
+  double* cst() { return reinterpret_cast<double*>(ws + off_cst); }
 };
 
 namespace {
@@ -487,6 +490,7 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
   g->off_lim = o; o = align256(o + 2 * sizeof(double));
   g->off_ttab = o; o = align256(o + TT_CAP * sizeof(double));
   g->off_bval = o; o = align256(o + (size_t)MAX_REPLAY * boundary_count(G) * sizeof(double));
+  g->off_cst = o; o = align256(o + (size_t)G.P * CL_NST * sizeof(double));
   g->need = o;
   choose_shape(g);
   *out = g;
@@ -596,6 +600,7 @@ pd_status pd_set_coefficients(pd_grid g, const pd_coeff_desc* c, void* stream) {
   g->lim_macro = lim[1];
   g->coeffs_set = true;
   g->tt_ok = false;
+  g->cst_ok = false;
   choose_shape(g);
   return PD_OK;
 }
@@ -960,3 +965,4 @@ pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
 }  // extern "C"
 
 #include "pd_batch_host.inc"
+#include "pd_closure_host.inc"

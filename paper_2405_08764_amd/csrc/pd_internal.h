@@ -207,4 +207,60 @@ hipError_t batch_blocks_per_cu(int nsb, size_t lds, int* out);
 hipError_t launch_batch_replay(const BurstArgs* inst, const pd_coeff_desc* const* descs, int n,
                                Clock* clk, int S, hipStream_t s);
 
+// ------------------------------------------------------------------ learned closure
+constexpr int CL_FEAT = 33;     // network inputs
+constexpr int CL_HID = 128;     // hidden width
+constexpr int CL_NPAR = CL_FEAT * CL_HID + CL_HID + CL_HID * CL_HID + CL_HID + CL_HID + 1;
+// offsets of the parameters in the flat FP32 vector: W1 [33][128], b1, W2 [128][128], b2,
+// w3 [128], b3
+constexpr int CL_OW1 = 0, CL_OB1 = CL_OW1 + CL_FEAT * CL_HID, CL_OW2 = CL_OB1 + CL_HID,
+              CL_OB2 = CL_OW2 + CL_HID * CL_HID, CL_OW3 = CL_OB2 + CL_HID,
+              CL_OB3 = CL_OW3 + CL_HID;
+// per-patch static closure data (doubles): node i, j; rates a, b, c, d; phi; scale factors
+// h1, h2; constant source at the centre; time-dependent source parts at the centre (2)
+constexpr int CL_NST = 12;
+hipError_t launch_closure_static(const Geo& g, const SrcInfo& src, const int* pmap,
+                                 const double* coef, long long plane, double* st,
+                                 hipStream_t s);
+constexpr int CL_K1P = 40;  // first-layer depth padded to a multiple of 8 (bfloat16 MFMA)
+
+struct MlpW {
+  const unsigned short *w1t, *w2t, *w3;
+  const float* par;  // FP32 biases b1, b2, b3 live in the master vector
+};
+
+struct ClosureArgs {
+  BurstArgs one;                  // single grid
+  const double* st_one;
+  double* fhat_one;
+  const BurstArgs* inst;          // batch: instance table (nullptr for a single grid)
+  const double* const* st_tab;    // batch: per-instance static closure data
+  double* const* fhat_tab;        // batch: per-instance F_hat
+  const int* items;               // batch: (instance, first patch) pairs
+  int n_items;
+  int k;                          // batch: step within the graph replay
+  MlpW W;
+  const float *mu, *sd;
+};
+
+hipError_t launch_closure_features(const Geo& g, const SrcInfo& src, const double* st,
+                                   const double* U, double t_n, float* X, double* F0,
+                                   double* sc, hipStream_t s);
+hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float* par,
+                            float* H1, float* A1, float* H2, float* A2, float* dH2,
+                            float* dH1, float* out, float* dout, float* grad, float* loss,
+                            hipStream_t s);
+hipError_t launch_adam(float* par, float* m, float* v, const float* g, int step, float lr,
+                       hipStream_t s);
+hipError_t launch_colstats(long long n, const float* X, float* mu, float* sd, hipStream_t s);
+hipError_t launch_standardise(long long n, const float* X, long long n_src, long long a,
+                              long long c, const float* mu, const float* sd, float* Xn,
+                              const float* y, float* yb, hipStream_t s);
+hipError_t launch_pack(const float* par, unsigned short* w1t, unsigned short* w2t,
+                       unsigned short* w3, hipStream_t s);
+hipError_t launch_mlp_infer(long long n, const float* Xn, const unsigned short* w1t,
+                            const unsigned short* w2t, const unsigned short* w3, const float* par,
+                            float* out, hipStream_t s);
+hipError_t launch_closure_step(const ClosureArgs& a, int blocks, hipStream_t s);
+
 }  // namespace pdk

@@ -135,6 +135,27 @@ EXPORTS = {
                                       C.c_void_p]),
     "pd_batch_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "pd_batch_sync": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pd_closure_create": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    "pd_closure_destroy": (C.c_int32, [C.c_void_p]),
+    "pd_closure_query": (C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int32)]),
+    "pd_closure_bind_workspace": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "pd_closure_set_params": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pd_closure_get_params": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "pd_closure_set_standardisation": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_closure_get_standardisation": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_closure_fit_standardisation": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64,
+                                                   C.c_void_p]),
+    "pd_closure_features": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_closure_gradients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                         C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_closure_train": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                     C.c_int32, C.c_float, C.c_uint32, C.c_void_p,
+                                     C.c_void_p]),
+    "pd_closure_infer": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.c_void_p]),
+    "pd_closure_patch_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
     "pd_last_error": (C.c_char_p, []),
 }
 
@@ -445,3 +466,93 @@ class Batch:
 
 BATCH_MENU = [(2, 1, 3), (2, 1, 5), (2, 1, 6), (2, 1, 7), (2, 2, 3), (1, 1, 5), (1, 1, 7),
               (1, 2, 3)]  # (exchange, columns, rows) of the batch kernel's menu, by index
+
+
+N_FEAT, N_PARAMS = 33, 20993
+
+
+class Closure:
+    """The learned closure's device state (pd_closure_*): parameters, optimiser moments,
+    standardisation, packed bfloat16 weights and training scratch in one workspace."""
+
+    def __init__(self, device=0, max_batch=8192):
+        import numpy as np
+        self.L = lib()
+        self.device = torch.device("cuda", device)
+        self.h = C.c_void_p()
+        _check(self.L.pd_closure_create(device, max_batch, C.byref(self.h)))
+        nbytes = C.c_size_t()
+        _check(self.L.pd_closure_query(self.h, C.byref(nbytes), None))
+        self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        _check(self.L.pd_closure_bind_workspace(self.h, C.c_void_p(base + (-base) % 256),
+                                                nbytes.value))
+        self.max_batch = max_batch
+        self._np = np
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            self.L.pd_closure_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def set_params(self, flat):
+        a = self._np.ascontiguousarray(flat, dtype=self._np.float32)
+        assert a.size == N_PARAMS
+        _check(self.L.pd_closure_set_params(self.h, a.ctypes.data_as(C.c_void_p)))
+
+    def params(self):
+        a = self._np.zeros(N_PARAMS, dtype=self._np.float32)
+        _check(self.L.pd_closure_get_params(self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def set_standardisation(self, mu, sd):
+        m = self._np.ascontiguousarray(mu, dtype=self._np.float32)
+        d = self._np.ascontiguousarray(sd, dtype=self._np.float32)
+        _check(self.L.pd_closure_set_standardisation(self.h, m.ctypes.data_as(C.c_void_p),
+                                                     d.ctypes.data_as(C.c_void_p)))
+
+    def standardisation(self):
+        m = self._np.zeros(N_FEAT, dtype=self._np.float32)
+        d = self._np.zeros(N_FEAT, dtype=self._np.float32)
+        _check(self.L.pd_closure_get_standardisation(self.h, m.ctypes.data_as(C.c_void_p),
+                                                     d.ctypes.data_as(C.c_void_p)))
+        return m, d
+
+    def fit_standardisation(self, X):
+        _check(self.L.pd_closure_fit_standardisation(self.h, _ptr(X), X.shape[0], _stream()))
+
+    def gradients(self, X, y):
+        g = torch.empty(N_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(self.L.pd_closure_gradients(self.h, _ptr(X), _ptr(y), X.shape[0], _ptr(g),
+                                           _ptr(loss), _stream()))
+        return g, loss
+
+    def train(self, X, y, batch=4096, epochs=1, lr=1e-3, seed=0):
+        losses = self._np.zeros(max(epochs, 1), dtype=self._np.float32)
+        _check(self.L.pd_closure_train(self.h, _ptr(X), _ptr(y), X.shape[0], batch, epochs,
+                                       float(lr), seed, losses.ctypes.data_as(C.c_void_p),
+                                       _stream()))
+        return losses[:epochs]
+
+    def infer(self, X):
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
+        _check(self.L.pd_closure_infer(self.h, _ptr(X), _ptr(out), X.shape[0], _stream()))
+        return out
+
+    @staticmethod
+    def features(grid, U, t_n):
+        X = torch.empty((grid.P, N_FEAT), dtype=torch.float32, device=grid.device)
+        F0 = torch.empty(grid.P, dtype=torch.float64, device=grid.device)
+        s = torch.empty(grid.P, dtype=torch.float64, device=grid.device)
+        _check(grid.L.pd_closure_features(grid.h, _ptr(U), float(t_n), _ptr(X), _ptr(F0),
+                                          _ptr(s), _stream()))
+        return X, F0, s
+
+    def patch_step(self, grid, U_n, t_n, out=None, dt_macro=None, with_fhat=False):
+        out = torch.empty_like(U_n) if out is None else out
+        fh = torch.empty(grid.P, dtype=torch.float64, device=grid.device) if with_fhat else None
+        dtm = grid.prob["time"]["dt_macro"] if dt_macro is None else dt_macro
+        _check(self.L.pd_closure_patch_step(self.h, grid.h, _ptr(U_n), _ptr(out), float(t_n),
+                                            float(dtm), _ptr(fh), _stream()))
+        return (out, fh) if with_fhat else out

@@ -296,11 +296,13 @@ pd_status pd_batch_sync(pd_batch b, void* stream);
  * and y_hat the network output on 33 inputs: the 24 differences of the 5x5 stencil / sigma
  * (row-major, centre skipped; indices wrap on a periodic axis, clamp otherwise),
  * U/(|U| + sigma), the five rates / kappa, q/(1+|q|) with q = g/(kappa (|U| + sigma)), and
- * the scale factors h1, h2 at the node; standardised per input.  Network 33 -> 128 -> 128 ->
- * 1 with GELU(x) = x Phi(x); parameters as one FP32 vector W1 [33][128] (input-major), b1,
- * W2 [128][128], b2, w3 [128], b3 (20993 values).  Training runs in FP32 (mean squared
- * error, Adam with beta1 0.9, beta2 0.999, eps 1e-8); inference rounds inputs, weights and
- * first-layer activations to bfloat16 and accumulates in FP32 on MFMA.  All pointers are
+ * the micro cell Peclet numbers P/(1+P), P = |nu| dxi/(2 alpha) and |omega| deta/(2 gamma)
+ * (the scale factors enter through alpha, gamma, nu, omega); standardised per input.
+ * Network 33 -> 128 -> 128 -> 1 with GELU(x) = x Phi(x); parameters as one FP32 vector
+ * W1 [33][128] (input-major), b1, W2 [128][128], b2, w3 [128], b3 (20993 values).  Training
+ * runs in FP32 (mean squared error on standardised targets, Adam with beta1 0.9, beta2
+ * 0.999, eps 1e-8); inference rounds inputs, weights and first-layer activations to
+ * bfloat16 and accumulates in FP32 on MFMA.  All pointers are
  * device pointers unless named host_. */
 typedef struct pd_closure_s* pd_closure;
 /* max_batch: rows per training step and per inference chunk (64..4194304). */
@@ -313,14 +315,24 @@ pd_status pd_closure_bind_workspace(pd_closure c, void* dev, size_t bytes);
 pd_status pd_closure_set_params(pd_closure c, const float* host_params);
 pd_status pd_closure_get_params(pd_closure c, float* host_params);
 /* Per-input mean and standard deviation (33 each, host), or fitted on the device to rows
- * X [n][33] of raw inputs. */
+ * X [n][33] of raw inputs (and, when y is non-NULL, the target mean and deviation from
+ * targets y [n]: the network learns (y - mean)/deviation and y_hat = mean + deviation out;
+ * by default mean 0, deviation 1). */
 pd_status pd_closure_set_standardisation(pd_closure c, const float* host_mu, const float* host_sd);
 pd_status pd_closure_get_standardisation(pd_closure c, float* host_mu, float* host_sd);
-pd_status pd_closure_fit_standardisation(pd_closure c, const float* X, int64_t n, void* stream);
+pd_status pd_closure_fit_standardisation(pd_closure c, const float* X, const float* y, int64_t n,
+                                         void* stream);
+pd_status pd_closure_set_target_scale(pd_closure c, float mean, float sd);
+pd_status pd_closure_get_target_scale(pd_closure c, float* mean, float* sd);
 /* Raw inputs X [P][33] (FP32), F0 [P] and s [P] (FP64, may be NULL) of every patch of a
  * grid for the macro field U at time t_n. */
 pd_status pd_closure_features(pd_grid g, const double* U, double t_n, float* X, double* F0,
                               double* s, void* stream);
+/* Training pairs of one plain macro step U_n -> U_np1 (e.g. pd_macro_step) of every
+ * patch: inputs X [P][33] and targets y [P] = (F - F0)/s clipped to [-10, 10], with
+ * F = (U_np1 - U_n)/dt_macro at the patch node (eq. Extrapolation solved for F). */
+pd_status pd_closure_targets(pd_grid g, const double* U_n, const double* U_np1, double t_n,
+                             double dt_macro, float* X, float* y, void* stream);
 /* Mean-squared-error loss (FP32 [1]) and gradients (FP32 [20993], layout of the
  * parameters) on n <= max_batch rows of raw inputs X and targets y. */
 pd_status pd_closure_gradients(pd_closure c, const float* X, const float* y, int32_t n,
@@ -331,7 +343,8 @@ pd_status pd_closure_gradients(pd_closure c, const float* X, const float* y, int
 pd_status pd_closure_train(pd_closure c, const float* X, const float* y, int64_t n,
                            int32_t batch, int32_t epochs, float lr, uint32_t seed,
                            float* host_losses, void* stream);
-/* Network outputs y_hat [n] (FP32) for raw inputs X [n][33], bfloat16 MFMA path. */
+/* Network outputs [n] (FP32, before the target scale) for raw inputs X [n][33], bfloat16
+ * MFMA path. */
 pd_status pd_closure_infer(pd_closure c, const float* X, float* out, int64_t n, void* stream);
 /* The closure macro step of every patch node of a grid: U_np1 = U_n + dt_macro F_hat
  * (boundary nodes untouched; F_hat [P] FP64 stored when non-NULL).  U_n, U_np1 distinct. */

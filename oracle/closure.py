@@ -19,10 +19,14 @@ coefficients of eq. (Computational_Problem) at the patch centre at time t_n:
 
 The 33 inputs (before standardisation): the 24 differences U(i+a, j+b) - U(i, j) of the
 5x5 stencil (a, b in -2..2, row-major in (b, a), centre skipped) divided by sigma; U/(|U| +
-sigma); a, b, c, d, phi divided by kappa; q/(1 + |q|) with q = g/(kappa (|U| + sigma)); the
-scale factors h1, h2 at the node.  Stencil indices wrap on a periodic axis and are clamped
-to the grid otherwise.  Network: 33 -> 128 -> 128 -> 1 with GELU(x) = x Phi(x) after the
-two hidden layers, trained on mean squared error with Adam.
+sigma); a, b, c, d, phi divided by kappa; q/(1 + |q|) with q = g/(kappa (|U| + sigma)); and
+the micro cell Peclet numbers P/(1 + P) in each direction, P_xi = |nu| dxi / (2 alpha) with
+the micro spacing dxi = h_xi/(m_xi - 1) (alpha = D11/h1^2 and nu carry the scale factors;
+the micro spacing sets the size of the micro-upwind error the network corrects).  Stencil
+indices wrap on a periodic axis and are clamped to the grid otherwise.  Network: 33 -> 128
+-> 128 -> 1 with GELU(x) = x Phi(x) after the two hidden layers, trained with Adam on the
+mean squared error of standardised targets (y - y_mean) / y_sd, so that y_hat = y_mean +
+y_sd out.  Training targets of a plain step: y = clip((F - F0) / s, -10, 10).
 
 Pins (tests/test_closure_oracle.py): F0 of linear and quadratic fields against closed
 forms, the stencil indexing against a brute-force construction, scale invariance of the
@@ -52,8 +56,8 @@ def tfactor(tf, t):
 
 
 def static_part(o):
-    """Per patch: node (i, j), centre coefficients, the rates a, b, c, d, the scale
-    factors h1, h2 at the node, and the source's spatial parts at the centre."""
+    """Per patch: node (i, j), centre coefficients, the rates a, b, c, d, the micro-to-
+    macro spacing ratios, and the source's spatial parts at the centre."""
     prob = o.prob
     gd = prob["grid"]
     pmap = o.patch_map()
@@ -67,10 +71,9 @@ def static_part(o):
         i, j = int(pmap[p, 0]), int(pmap[p, 1])
         al, ga, nu, om, ph = (coef[f, p, lc, kc] for f in range(5))
         src = [coef[5 + q, p, lc, kc] for q in range(len(prob["src"]))]
-        met = o.metric(gd["xi0"] + i * Dxi, gd["eta0"] + j * Deta)
         out.append({"i": i, "j": j, "a": al / (Dxi * Dxi), "b": ga / (Deta * Deta),
                     "c": nu / Dxi, "d": om / Deta, "phi": ph, "src": src,
-                    "h1": met[12], "h2": met[13]})
+                    "rx": gd["h_xi"] / (mx - 1) / Dxi, "re": gd["h_eta"] / (me - 1) / Deta})
     return out
 
 
@@ -117,9 +120,17 @@ def features(o, U, t_n, static=None):
         den = kappa * (abs(u) + sigma)
         q = g / den if den > 0.0 else 0.0
         X[p, 30] = q / (1.0 + abs(q))
-        X[p, 31] = e["h1"]
-        X[p, 32] = e["h2"]
+        pex = abs(c_) * e["rx"] / (2.0 * a_) if a_ > 0.0 else 0.0
+        pee = abs(d_) * e["re"] / (2.0 * b_) if b_ > 0.0 else 0.0
+        X[p, 31] = pex / (1.0 + pex)
+        X[p, 32] = pee / (1.0 + pee)
     return X, F0, s
+
+
+def targets(F, F0, s):
+    """Training targets of plain-scheme time derivatives F (see the module docstring)."""
+    y = np.where(s > 0.0, (F - F0) / np.where(s > 0.0, s, 1.0), 0.0)
+    return np.clip(y, -10.0, 10.0)
 
 
 # ------------------------------------------------------------------------------ network

@@ -2,8 +2,8 @@
 // the paper; the patch scheme produces its training targets and stays its fallback).
 //
 // Inputs of patch p at macro node (i, j): the 5x5 macro stencil (indices wrap on a
-// periodic axis, clamp otherwise), the coefficient rates at the patch centre and the scale
-// factors at the node.  The network predicts a correction to the macro finite-difference
+// periodic axis, clamp otherwise), the coefficient rates at the patch centre and the micro
+// cell Peclet numbers (which carry the scale factors and the micro spacing).  The network predicts a correction to the macro finite-difference
 // operator F0 at the node, scaled by s = kappa sigma + 1e-3 (|g| + |phi U|):
 // F_hat = F0 + s y_hat, then U_np1 = U + dt_macro F_hat (eq. Extrapolation).
 //
@@ -78,14 +78,20 @@ __device__ __forceinline__ void closure_features(const Geo& g, const SrcInfo& sr
   const double den = kappa * au;
   const double qq = den > 0.0 ? gsrc / den : 0.0;
   f.x[30] = (float)(qq / (1.0 + fabs(qq)));
-  f.x[31] = (float)st[7];
-  f.x[32] = (float)st[8];
+  // micro cell Peclet numbers |nu| dxi / (2 alpha), |omega| deta / (2 gamma), squashed
+  const double pex = a_ > 0.0 ? fabs(c_) * st[7] / (2.0 * a_) : 0.0;
+  const double pee = b_ > 0.0 ? fabs(d_) * st[8] / (2.0 * b_) : 0.0;
+  f.x[31] = (float)(pex / (1.0 + pex));
+  f.x[32] = (float)(pee / (1.0 + pee));
 }
 
+// Inputs of every patch; with U_np1 also the training target of the step U -> U_np1,
+// y = (F - F0) / s clipped to [-10, 10] with F = (U_np1 - U) / dt_macro at the node.
 __global__ void k_closure_features(Geo g, SrcInfo src, const double* __restrict__ st,
                                    const double* __restrict__ U, double t_n,
                                    float* __restrict__ X, double* __restrict__ F0,
-                                   double* __restrict__ sc) {
+                                   double* __restrict__ sc, const double* __restrict__ Unp1,
+                                   double dtm, float* __restrict__ y) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.P) return;
   Feat f;
@@ -93,6 +99,12 @@ __global__ void k_closure_features(Geo g, SrcInfo src, const double* __restrict_
   for (int q = 0; q < CL_FEAT; ++q) X[(long long)p * CL_FEAT + q] = f.x[q];
   if (F0) F0[p] = f.F0;
   if (sc) sc[p] = f.s;
+  if (y) {
+    const double F = (Unp1[f.node] - f.u) / dtm;
+    double t = f.s > 0.0 ? (F - f.F0) / f.s : 0.0;
+    t = t > 10.0 ? 10.0 : (t < -10.0 ? -10.0 : t);
+    y[p] = (float)t;
+  }
 }
 
 // ------------------------------------------------------------------------- training
@@ -286,17 +298,47 @@ __global__ void k_colstats(long long n, const float* __restrict__ X, float* __re
 
 // Xn = (X - mu) / sd, optionally gathering rows through an affine permutation
 // row(r) = (a r + c) mod n_src (a coprime to n_src): a cheap seeded shuffle.
+// Targets are standardised with ys = {mean, deviation}.
 __global__ void k_standardise(long long n, const float* __restrict__ X, long long n_src,
                               long long a, long long c, const float* __restrict__ mu,
                               const float* __restrict__ sd, float* __restrict__ Xn,
-                              const float* __restrict__ y, float* __restrict__ yb) {
+                              const float* __restrict__ y, float* __restrict__ yb,
+                              const float* __restrict__ ys) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * CL_FEAT) return;
   const long long r = e / CL_FEAT;
   const int q = (int)(e - r * CL_FEAT);
   const long long src = n_src > 0 ? (a * r + c) % n_src : r;
   Xn[e] = (X[src * CL_FEAT + q] - mu[q]) / sd[q];
-  if (yb && q == 0) yb[r] = y[src];
+  if (yb && q == 0) yb[r] = (y[src] - ys[0]) / ys[1];
+}
+
+// Mean and deviation (floor 1e-12) of n targets, one block.
+__global__ void k_target_stats(long long n, const float* __restrict__ y, float* __restrict__ ys) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (long long r = threadIdx.x; r < n; r += 256) s += y[r];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)n;
+  __syncthreads();
+  double q = 0.0;
+  for (long long r = threadIdx.x; r < n; r += 256) q += (y[r] - mean) * (y[r] - mean);
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double var = red[0] / (double)n;
+    ys[0] = (float)mean;
+    ys[1] = (float)sqrt(var > 1e-24 ? var : 1e-24);
+  }
 }
 
 // ------------------------------------------------------------------------- inference
@@ -482,7 +524,7 @@ __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
   __syncthreads();
   mlp_tile(Cl.W, xt, ht, part, res);
   if (t < 64 && p0 + t < A.g.P) {
-    const double Fh = sF0[t] + sS[t] * (double)res[t];
+    const double Fh = sF0[t] + sS[t] * ((double)Cl.ys[0] + (double)Cl.ys[1] * (double)res[t]);
     const double un = sU[t] + A.dt_macro * Fh;
     Uout[sNode[t]] = un;
     if (fhat) fhat[p0 + t] = Fh;
@@ -496,9 +538,10 @@ __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
 
 hipError_t launch_closure_features(const Geo& g, const SrcInfo& src, const double* st,
                                    const double* U, double t_n, float* X, double* F0,
-                                   double* sc, hipStream_t s) {
+                                   double* sc, const double* Unp1, double dtm, float* y,
+                                   hipStream_t s) {
   hipLaunchKernelGGL(k_closure_features, dim3((g.P + 127) / 128), dim3(128), 0, s, g, src, st,
-                     U, t_n, X, F0, sc);
+                     U, t_n, X, F0, sc, Unp1, dtm, y);
   return hipGetLastError();
 }
 
@@ -546,10 +589,15 @@ hipError_t launch_colstats(long long n, const float* X, float* mu, float* sd, hi
 
 hipError_t launch_standardise(long long n, const float* X, long long n_src, long long a,
                               long long c, const float* mu, const float* sd, float* Xn,
-                              const float* y, float* yb, hipStream_t s) {
+                              const float* y, float* yb, const float* ys, hipStream_t s) {
   const long long e = n * CL_FEAT;
   hipLaunchKernelGGL(k_standardise, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, s, n, X,
-                     n_src, a, c, mu, sd, Xn, y, yb);
+                     n_src, a, c, mu, sd, Xn, y, yb, ys);
+  return hipGetLastError();
+}
+
+hipError_t launch_target_stats(long long n, const float* y, float* ys, hipStream_t s) {
+  hipLaunchKernelGGL(k_target_stats, dim3(1), dim3(256), 0, s, n, y, ys);
   return hipGetLastError();
 }
 

@@ -384,7 +384,7 @@ __global__ void k_batch_replay(const BurstArgs* __restrict__ inst,
 
 // Static inputs of the learned closure per patch: the coefficients at the patch centre
 // as rates on the macro spacing (alpha/Dxi^2, gamma/Deta^2, nu/Dxi, omega/Deta), phi, the
-// scale factors h1, h2 at the node, and the source's spatial parts at the centre.
+// micro-to-macro spacing ratios, and the source's spatial parts at the centre.
 __global__ void k_closure_static(Geo g, SrcInfo src, const int* __restrict__ pmap,
                                  const double* __restrict__ coef, long long plane,
                                  double* __restrict__ st) {
@@ -393,8 +393,6 @@ __global__ void k_closure_static(Geo g, SrcInfo src, const int* __restrict__ pma
   const int i = pmap[11 * p], j = pmap[11 * p + 1];
   const long long at =
       (long long)p * g.m_xi * g.m_eta + (long long)(g.m_eta / 2) * g.m_xi + g.m_xi / 2;
-  Metric m;
-  metric_at(g, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, m);
   double* o = st + (long long)p * CL_NST;
   o[0] = i;
   o[1] = j;
@@ -403,8 +401,8 @@ __global__ void k_closure_static(Geo g, SrcInfo src, const int* __restrict__ pma
   o[4] = coef[2 * plane + at] / g.Dxi;
   o[5] = coef[3 * plane + at] / g.Deta;
   o[6] = coef[4 * plane + at];
-  o[7] = sqrt(m.x_s * m.x_s + m.y_s * m.y_s);
-  o[8] = sqrt(m.x_e * m.x_e + m.y_e * m.y_e);
+  o[7] = g.dxi / g.Dxi;
+  o[8] = g.deta / g.Deta;
   double gc = 0.0;
   for (int c = 0; c < src.nconst; ++c) gc += src.ca[c] * coef[src.plane_c[c] * plane + at];
   o[9] = gc;

@@ -216,8 +216,9 @@ constexpr int CL_NPAR = CL_FEAT * CL_HID + CL_HID + CL_HID * CL_HID + CL_HID + C
 constexpr int CL_OW1 = 0, CL_OB1 = CL_OW1 + CL_FEAT * CL_HID, CL_OW2 = CL_OB1 + CL_HID,
               CL_OB2 = CL_OW2 + CL_HID * CL_HID, CL_OW3 = CL_OB2 + CL_HID,
               CL_OB3 = CL_OW3 + CL_HID;
-// per-patch static closure data (doubles): node i, j; rates a, b, c, d; phi; scale factors
-// h1, h2; constant source at the centre; time-dependent source parts at the centre (2)
+// per-patch static closure data (doubles): node i, j; rates a, b, c, d; phi; micro-to-macro
+// spacing ratios dxi/Dxi, deta/Deta; constant source at the centre; time-dependent source
+// parts at the centre (2)
 constexpr int CL_NST = 12;
 hipError_t launch_closure_static(const Geo& g, const SrcInfo& src, const int* pmap,
                                  const double* coef, long long plane, double* st,
@@ -241,11 +242,13 @@ struct ClosureArgs {
   int k;                          // batch: step within the graph replay
   MlpW W;
   const float *mu, *sd;
+  const float* ys;                // target mean and deviation: y = ys[0] + ys[1] out
 };
 
 hipError_t launch_closure_features(const Geo& g, const SrcInfo& src, const double* st,
                                    const double* U, double t_n, float* X, double* F0,
-                                   double* sc, hipStream_t s);
+                                   double* sc, const double* Unp1, double dtm, float* y,
+                                   hipStream_t s);
 hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float* par,
                             float* H1, float* A1, float* H2, float* A2, float* dH2,
                             float* dH1, float* out, float* dout, float* grad, float* loss,
@@ -255,7 +258,8 @@ hipError_t launch_adam(float* par, float* m, float* v, const float* g, int step,
 hipError_t launch_colstats(long long n, const float* X, float* mu, float* sd, hipStream_t s);
 hipError_t launch_standardise(long long n, const float* X, long long n_src, long long a,
                               long long c, const float* mu, const float* sd, float* Xn,
-                              const float* y, float* yb, hipStream_t s);
+                              const float* y, float* yb, const float* ys, hipStream_t s);
+hipError_t launch_target_stats(long long n, const float* y, float* ys, hipStream_t s);
 hipError_t launch_pack(const float* par, unsigned short* w1t, unsigned short* w2t,
                        unsigned short* w3, hipStream_t s);
 hipError_t launch_mlp_infer(long long n, const float* Xn, const unsigned short* w1t,

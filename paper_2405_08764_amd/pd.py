@@ -143,10 +143,15 @@ EXPORTS = {
     "pd_closure_get_params": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pd_closure_set_standardisation": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_closure_get_standardisation": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
-    "pd_closure_fit_standardisation": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64,
-                                                   C.c_void_p]),
+    "pd_closure_fit_standardisation": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                                   C.c_int64, C.c_void_p]),
+    "pd_closure_set_target_scale": (C.c_int32, [C.c_void_p, C.c_float, C.c_float]),
+    "pd_closure_get_target_scale": (C.c_int32, [C.c_void_p, C.POINTER(C.c_float),
+                                                C.POINTER(C.c_float)]),
     "pd_closure_features": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_closure_targets": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                       C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_closure_gradients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_closure_train": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
@@ -518,8 +523,17 @@ class Closure:
                                                      d.ctypes.data_as(C.c_void_p)))
         return m, d
 
-    def fit_standardisation(self, X):
-        _check(self.L.pd_closure_fit_standardisation(self.h, _ptr(X), X.shape[0], _stream()))
+    def fit_standardisation(self, X, y=None):
+        _check(self.L.pd_closure_fit_standardisation(self.h, _ptr(X), _ptr(y), X.shape[0],
+                                                     _stream()))
+
+    def set_target_scale(self, mean, sd):
+        _check(self.L.pd_closure_set_target_scale(self.h, float(mean), float(sd)))
+
+    def target_scale(self):
+        m, s = C.c_float(), C.c_float()
+        _check(self.L.pd_closure_get_target_scale(self.h, C.byref(m), C.byref(s)))
+        return m.value, s.value
 
     def gradients(self, X, y):
         g = torch.empty(N_PARAMS, dtype=torch.float32, device=self.device)
@@ -548,6 +562,14 @@ class Closure:
         _check(grid.L.pd_closure_features(grid.h, _ptr(U), float(t_n), _ptr(X), _ptr(F0),
                                           _ptr(s), _stream()))
         return X, F0, s
+
+    @staticmethod
+    def targets(grid, U_n, U_np1, t_n, dt_macro, X=None, y=None):
+        X = torch.empty((grid.P, N_FEAT), dtype=torch.float32, device=grid.device) if X is None else X
+        y = torch.empty(grid.P, dtype=torch.float32, device=grid.device) if y is None else y
+        _check(grid.L.pd_closure_targets(grid.h, _ptr(U_n), _ptr(U_np1), float(t_n),
+                                         float(dt_macro), _ptr(X), _ptr(y), _stream()))
+        return X, y
 
     def patch_step(self, grid, U_n, t_n, out=None, dt_macro=None, with_fhat=False):
         out = torch.empty_like(U_n) if out is None else out

@@ -148,3 +148,28 @@ def test_bf16_rounding_bit_patterns(cl):
              (one + ulp / 2 + 2 ** -20, one + ulp), (-(one + ulp), -(one + ulp)), (0.0, 0.0)]
     for x, want in cases:
         assert cl.bf16(np.array([x]))[0] == want, (x, cl.bf16(np.array([x]))[0], want)
+
+
+def test_micro_peclet_inputs_of_constant_coefficients(oracle_mod, cl):
+    """Constant D and v on the untransformed square (beta = 0): the last two inputs are
+    P/(1+P) with P = |v| dxi / (2 D) in each direction."""
+    p = W.config4_instance(2, n_range=(9, 9), m_range=(7, 7))
+    assert p["grid"]["geometry"] == "tanh"
+    p["grid"]["gparam"] = 0.0
+    eps, v1, v2 = 2e-3, 0.8, -0.3
+    p["fields"] = {"D11": W.field(c0=eps), "D22": W.field(c0=eps), "v1": W.field(c0=v1),
+                   "v2": W.field(c0=v2), "f": W.field(c0=0.5)}
+    o = oracle_mod.Oracle(p)
+    U = np.ones((9, 9))
+    X, _, _ = cl.features(o, U, 0.0)
+    dx = p["grid"]["h_xi"] / (7 - 1)
+    for k, v in ((31, v1), (32, v2)):
+        P = abs(v) * dx / (2 * eps)
+        np.testing.assert_allclose(X[:, k], P / (1 + P), rtol=1e-12)
+
+
+def test_targets_recover_the_correction(cl):
+    F0 = np.array([1.0, -2.0, 0.5, 3.0])
+    s = np.array([0.1, 0.2, 0.0, 1e-3])
+    F = np.array([1.05, -2.1, 7.0, 4.0])
+    np.testing.assert_allclose(cl.targets(F, F0, s), [0.5, -0.5, 0.0, 10.0])

@@ -351,6 +351,22 @@ pd_status pd_closure_infer(pd_closure c, const float* X, float* out, int64_t n, 
 pd_status pd_closure_patch_step(pd_closure c, pd_grid g, const double* U_n, double* U_np1,
                                 double t_n, double dt_macro, double* F_hat, void* stream);
 
+/* Batched closure steps with the plain scheme as fallback.  Each macro step of every
+ * member: the closure step of all patch nodes (and the Dirichlet nodes), then plain bursts
+ * on one work item in `stride` of each member (a per-step hashed choice, at least one
+ * item per member) which overwrite those patches, the residual |F_hat - F| / s of every
+ * checked patch, and, for each member whose largest residual exceeds `threshold` (or is
+ * not finite), plain bursts on all its items in the same step.  All in one HIP graph per
+ * 16 steps.  Attach needs pd_batch_closure_bytes of device memory (256-byte aligned) and
+ * a closure with parameters and standardisation set; the closure must outlive the batch's
+ * use of it.  Stats: patches checked and member fallbacks since the last reset. */
+pd_status pd_batch_closure_bytes(pd_batch b, size_t* bytes);
+pd_status pd_batch_closure_attach(pd_batch b, pd_closure c, int32_t stride, double threshold,
+                                  void* dev, size_t bytes);
+pd_status pd_batch_closure_solve(pd_batch b, int32_t n_steps, void* stream);
+pd_status pd_batch_closure_stats(pd_batch b, int64_t* checked, int64_t* fallbacks,
+                                 int32_t reset);
+
 const char* pd_last_error(void);
 
 #ifdef __cplusplus

@@ -39,8 +39,20 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch(BatchArgs B) {
     if (threadIdx.x == 0) s_item = atomicAdd(B.head, 1);
     __syncthreads();
     const int it = s_item;
-    if (it >= B.n_items) break;
-    const BatchItem I = B.items[it];
+    const int n_items = B.n_dev != nullptr ? *B.n_dev : B.n_items;
+    if (it >= n_items) break;
+    int idx = it;
+    if (B.segs != nullptr) {  // segment of `it`: the last with prefix <= it
+      int lo = 0, hi = B.n_segs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (B.segs[mid].w <= it) lo = mid;
+        else hi = mid - 1;
+      }
+      const int4 sg = B.segs[lo];
+      idx = sg.x + (it - sg.w) * sg.z;
+    }
+    const BatchItem I = B.items[idx];
     const BurstArgs& A = B.inst[I.inst];
     const long long n = B.tuning ? 0 : B.clk->base + B.k;
     const double* Uin = (n & 1) ? A.Unew : A.U;
@@ -72,7 +84,116 @@ __global__ __launch_bounds__(BATCH_THREADS) void k_batch(BatchArgs B) {
   }
 }
 
+// Patches of an item: BATCH_WAVES teams for in-wave shapes, one team otherwise.
+__device__ inline int item_patches(const BatchItem& I) {
+  switch (I.shape) {
+#define PD_XW(id, xch, C_, R_) \
+  case id: return (xch == XCH_LANES ? BATCH_WAVES : 1) * I.ppb;
+    PD_BATCH_MENU(PD_XW)
+#undef PD_XW
+    default: return I.ppb;
+  }
+}
+
+// One block: this step's spot-check segments (per instance, every stride-th item from a
+// hashed offset, at least one item), their prefix sums and total; clears the residuals.
+__global__ void k_spot_segments(SpotArgs S) {
+  const long long step = S.clk->base + S.k;
+  for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+    const int cnt = S.count[i];
+    unsigned int h = (unsigned int)(step * 2654435761ull) ^ (unsigned int)(i * 40503u + 17u);
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    const int off = (int)(h % (unsigned int)S.stride);
+    int c = cnt > off ? (cnt - 1 - off) / S.stride + 1 : 0;
+    int f = off;
+    if (c == 0 && cnt > 0) {
+      c = 1;
+      f = (int)(h % (unsigned int)cnt);
+    }
+    S.spot[i] = make_int4(S.first[i] + f, c, S.stride, 0);
+    S.resid[i] = 0u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // sequential prefix (a few hundred instances)
+    int run = 0;
+    for (int i = 0; i < S.n; ++i) {
+      S.spot[i].w = run;
+      run += S.spot[i].y;
+    }
+    *S.spot_n = run;
+  }
+}
+
+// Residuals of the checked patches: |F_hat - F| / s with F from the plain step just
+// written, per-instance maximum.  Blocks stride over the spot items.
+__global__ void k_spot_residuals(SpotArgs S, const BurstArgs* __restrict__ inst,
+                                 const BatchItem* __restrict__ items,
+                                 double* const* __restrict__ fhat,
+                                 float* const* __restrict__ sres) {
+  const int total = *S.spot_n;
+  const long long step = S.clk->base + S.k;
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    int lo = 0, hi = S.n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (S.spot[mid].w <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const int4 sg = S.spot[lo];
+    const BatchItem I = items[sg.x + (it - sg.w) * sg.z];
+    const BurstArgs& A = inst[I.inst];
+    const double* Uin = (step & 1) ? A.Unew : A.U;
+    const double* Uout = (step & 1) ? A.U : A.Unew;
+    const int np = item_patches(I);
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+      const long long p = (long long)I.p0 + q;
+      if (p >= A.g.P) continue;
+      const int node = A.pmap[11 * p + 6];
+      const double F = (Uout[node] - Uin[node]) / A.dt_macro;
+      const double r = fabs(fhat[I.inst][p] - F) / (double)sres[I.inst][p];
+      const float rf = (float)(r == r ? r : 1e30);
+      atomicMax(&S.resid[I.inst], __float_as_uint(rf));
+      atomicAdd(&S.stats[0], 1ull);
+    }
+  }
+}
+
+// One block: fallback segments (every item of each instance whose residual exceeds the
+// threshold) and their count.
+__global__ void k_redo_segments(SpotArgs S) {
+  if (threadIdx.x != 0) return;
+  int run = 0, bad = 0;
+  for (int i = 0; i < S.n; ++i) {
+    const float r = __uint_as_float(S.resid[i]);
+    const bool redo = !((double)r <= S.threshold);
+    S.redo[i] = make_int4(S.first[i], redo ? S.count[i] : 0, 1, run);
+    run += redo ? S.count[i] : 0;
+    bad += redo ? 1 : 0;
+  }
+  *S.redo_n = run;
+  if (bad) atomicAdd(&S.stats[1], (unsigned long long)bad);
+}
+
 }  // namespace
+
+hipError_t launch_spot_segments(const SpotArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_spot_segments, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_redo_segments(const SpotArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_redo_segments, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spot_residuals(const SpotArgs& a, const BurstArgs* inst,
+                                 const BatchItem* items, double* const* fhat,
+                                 float* const* sres, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_spot_residuals, dim3(blocks), dim3(256), 0, s, a, inst, items, fhat, sres);
+  return hipGetLastError();
+}
 
 hipError_t launch_batch(int nsb, const BatchArgs& a, int blocks, size_t lds, hipStream_t s) {
   if (nsb == 2)

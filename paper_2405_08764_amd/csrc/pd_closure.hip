@@ -528,6 +528,7 @@ __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
     const double un = sU[t] + A.dt_macro * Fh;
     Uout[sNode[t]] = un;
     if (fhat) fhat[p0 + t] = Fh;
+    if (batch && Cl.sres_tab) Cl.sres_tab[inst][p0 + t] = (float)sS[t];
     if (!isfinite(un)) atomicOr(A.flag, 1);
   }
 }

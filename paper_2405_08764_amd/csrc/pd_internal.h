@@ -197,7 +197,36 @@ struct BatchArgs {
   const Clock* clk;         // macro step = clk->base + k (buffers by its parity)
   int k;                    // step within the graph replay
   int tuning;               // 1: read buffer 0, write buffer 1, whatever the clock says
+  // segment mode (device-built lists): item j of the launch is
+  // items[seg.first + (j - seg.prefix) seg.stride] of the segment holding j, with the
+  // item count read from n_dev
+  const int4* segs;         // {first, count, stride, prefix} per segment, or nullptr
+  int n_segs;
+  const int* n_dev;
 };
+
+// Spot checks and fallback of the batched closure (device-side state, one entry per
+// instance).  first/count: the instance's items in the instance-ordered item list.
+struct SpotArgs {
+  const int* first;
+  const int* count;
+  int n;                    // instances
+  int stride;               // one item in `stride` is checked per step
+  const Clock* clk;
+  int k;
+  int4* spot;               // spot-check segments, and their item count in spot_n
+  int* spot_n;
+  int4* redo;               // fallback segments and count
+  int* redo_n;
+  unsigned int* resid;      // per-instance maximum residual (float bits)
+  double threshold;
+  unsigned long long* stats;  // [0] patches checked, [1] instance fallbacks
+};
+hipError_t launch_spot_segments(const SpotArgs& a, hipStream_t s);
+hipError_t launch_redo_segments(const SpotArgs& a, hipStream_t s);
+hipError_t launch_spot_residuals(const SpotArgs& a, const BurstArgs* inst,
+                                 const BatchItem* items, double* const* fhat,
+                                 float* const* sres, int blocks, hipStream_t s);
 
 // Persistent batch kernel, nsb = 1 or 2 time-dependent source terms at most.
 hipError_t launch_batch(int nsb, const BatchArgs& a, int blocks, size_t lds, hipStream_t s);
@@ -240,6 +269,7 @@ struct ClosureArgs {
   const int* items;               // batch: (instance, first patch) pairs
   int n_items;
   int k;                          // batch: step within the graph replay
+  float* const* sres_tab;         // batch: per-instance closure scale s (spot residuals)
   MlpW W;
   const float *mu, *sd;
   const float* ys;                // target mean and deviation: y = ys[0] + ys[1] out

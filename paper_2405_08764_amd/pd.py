@@ -161,6 +161,12 @@ EXPORTS = {
                                      C.c_void_p]),
     "pd_closure_patch_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "pd_batch_closure_bytes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t)]),
+    "pd_batch_closure_attach": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                                            C.c_void_p, C.c_size_t]),
+    "pd_batch_closure_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "pd_batch_closure_stats": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_int64), C.c_int32]),
     "pd_last_error": (C.c_char_p, []),
 }
 
@@ -467,6 +473,27 @@ class Batch:
 
     def sync(self):
         _check(self.L.pd_batch_sync(self.h, _stream()))
+
+    def attach_closure(self, closure, stride=100, threshold=1.0):
+        """Use `closure` for closure_solve, checking one item in `stride` per member and
+        step and falling back to the plain scheme above `threshold`."""
+        nbytes = C.c_size_t()
+        _check(self.L.pd_batch_closure_bytes(self.h, C.byref(nbytes)))
+        self.cl_ws = torch.empty(nbytes.value + 256, dtype=torch.uint8,
+                                 device=self.grids[0].device)
+        base = self.cl_ws.data_ptr()
+        _check(self.L.pd_batch_closure_attach(self.h, closure.h, int(stride), float(threshold),
+                                              C.c_void_p(base + (-base) % 256), nbytes.value))
+        self.closure = closure
+
+    def closure_solve(self, n_steps):
+        _check(self.L.pd_batch_closure_solve(self.h, int(n_steps), _stream()))
+        return self.U
+
+    def closure_stats(self, reset=False):
+        a, b = C.c_int64(), C.c_int64()
+        _check(self.L.pd_batch_closure_stats(self.h, C.byref(a), C.byref(b), int(reset)))
+        return a.value, b.value
 
 
 BATCH_MENU = [(2, 1, 3), (2, 1, 5), (2, 1, 6), (2, 1, 7), (2, 2, 3), (1, 1, 5), (1, 1, 7),

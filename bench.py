@@ -205,14 +205,120 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_closure(args):
+    """The mixed batch with the learned closure standing in for the micro-bursts (1% of
+    the work items re-run by the plain scheme each step as spot checks, per-member
+    fallback), against the plain batched scheme on the same batch."""
+    import numpy as np
+    import torch
+
+    from paper_2405_08764_amd import closure_train as T
+    from paper_2405_08764_amd import pd
+    from paper_2405_08764_amd import workloads as W
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    N = args.steps
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        t_setup = time.perf_counter()
+        grids = T.instance_grids(args.instances, W.MASTER_SEED + 4000, N)
+        U0 = [g.initial() for g in grids]
+        B = pd.Batch(grids, [u.clone() for u in U0])
+        B.autotune(reps=2)
+        log(f"batch of {len(grids)} ready in {time.perf_counter() - t_setup:.1f} s")
+        # plain scheme
+        B.solve(2)
+        torch.cuda.synchronize()
+        for u, u0 in zip(B.U, U0):
+            u.copy_(u0)
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        B.solve(N)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - s
+        ref = [u.clone() for u in B.U]
+        log(f"plain: {N / t_plain:.3f} batch steps/s")
+        # training pairs from plain steps of disjoint instances, training
+        s = time.perf_counter()
+        tg = T.instance_grids(args.train_instances, T.TRAIN_SEED, 40)
+        X, y = T.generate(tg, steps=16, every=2, max_pairs=args.train_pairs)
+        n_pairs = int(X.shape[0])
+        torch.cuda.synchronize()
+        t_gen = time.perf_counter() - s
+        s = time.perf_counter()
+        C, losses = T.train(X, y, epochs=args.epochs, batch=4096, lr=2e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - s
+        ym, ysd = C.target_scale()
+        rms = float(np.sqrt(losses[-1])) * ysd  # residual RMS in units of s
+        threshold = args.threshold_factor * rms
+        log(f"pairs {X.shape[0]} generated in {t_gen:.1f} s, trained in {t_train:.1f} s, "
+            f"loss {losses[0]:.4g} -> {losses[-1]:.4g}, threshold {threshold:.3g}")
+        del tg, X, y
+        # closure scheme
+        B.attach_closure(C, stride=100, threshold=threshold)
+        B.closure_solve(2)
+        torch.cuda.synchronize()
+        for u, u0 in zip(B.U, U0):
+            u.copy_(u0)
+        B.closure_stats(reset=True)
+        torch.cuda.synchronize()
+        s = time.perf_counter()
+        B.closure_solve(N)
+        torch.cuda.synchronize()
+        t_cl = time.perf_counter() - s
+        checked, fallbacks = B.closure_stats()
+        errs = np.array([T.rel_l2(a, b) for a, b in zip(B.U, ref)])
+        # the baseline operator alone, for what the network adds
+        Z = T.zero_closure(C)
+        for u, u0 in zip(B.U, U0):
+            u.copy_(u0)
+        B.attach_closure(Z, stride=100, threshold=1e30)
+        B.closure_solve(N)
+        torch.cuda.synchronize()
+        errs0 = np.array([T.rel_l2(a, b) for a, b in zip(B.U, ref)])
+    info = B.query()
+    P = sum(g.P for g in grids)
+    out = {
+        "metric": "macro steps/s of the batched scheme with the learned closure vs plain",
+        "value": N / t_cl,
+        "unit": "batch macro steps/s",
+        "n_gpus": 1, "steps": N, "warmup": 2, "ms_per_step": t_cl / N * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MFMA (fp32 accumulate) closure, f64 plain fallback",
+        "data": "synthetic (seeded analytic coefficients, no dataset)",
+        "config": {"workload": f"config5: learned closure on the config4 batch of "
+                               f"{len(grids)} instances, 1% spot checks per step",
+                   "patches": P, "updates_per_step_plain": info.updates_per_step},
+        "plain_macro_steps_per_s": N / t_plain,
+        "speedup_vs_plain": t_plain / t_cl,
+        "rel_l2_vs_plain": {"max": float(errs.max()), "mean": float(errs.mean())},
+        "rel_l2_baseline_operator_only": {"max": float(errs0.max()), "mean": float(errs0.mean())},
+        "spot_checks": {"patches_checked": checked, "fraction": checked / (P * N),
+                        "member_fallbacks": fallbacks, "threshold": threshold},
+        "training": {"pairs": n_pairs, "epochs": args.epochs,
+                     "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                     "generate_s": t_gen, "train_s": t_train},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed macro steps (default 1000; 10 for config4, 20 for config5)")
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config3", "config4"])
+                    choices=["config1", "config2", "config3", "config4", "config5"])
+    ap.add_argument("--train-instances", type=int, default=96,
+                    help="config5: training instances (seeds disjoint from the batch)")
+    ap.add_argument("--train-pairs", type=int, default=2_000_000,
+                    help="config5: training pairs from plain steps")
+    ap.add_argument("--epochs", type=int, default=25, help="config5: training epochs")
+    ap.add_argument("--threshold-factor", type=float, default=10.0,
+                    help="config5: fallback threshold in units of the training residual RMS")
     ap.add_argument("--instances", type=int, default=512,
                     help="config4: number of mixed instances in the batch")
     ap.add_argument("--kernel-reps", type=int, default=64)
@@ -232,6 +338,8 @@ def main():
     ap.add_argument("--pmc-shape", default="", help="launch shape the counters were taken at")
     ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"config4": 10, "config5": 20}.get(args.workload, 1000)
     if args.pmc_summary:
         kernel = KERNEL_NAME[int(args.pmc_shape.split(",")[0])]
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], kernel + "<",
@@ -252,6 +360,8 @@ def main():
 
     if args.workload == "config4":
         return bench_batch(args)
+    if args.workload == "config5":
+        return bench_closure(args)
     prob, desc = workload(args.workload)
     t = prob["time"]
     torch.cuda.set_device(0)

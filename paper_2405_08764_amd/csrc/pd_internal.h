@@ -114,6 +114,8 @@ struct BurstArgs {
   int n_t;
   int ppb;                // patches per block
   int* flag;              // non-finite flag
+  int balance;            // in-wave kernels: every block is resident at once, so waves
+                          // lower their issue priority as they progress (set at launch)
 };
 
 // Launchers implemented in the kernel translation units.
@@ -150,8 +152,8 @@ bool burst_shape_supported(int R, int C);
 
 // Dynamic LDS bytes of a burst launch: the lane-major exchange tiles (double-buffered,
 // guard of lanes-per-band + 1 words on both sides) or the FP64 lifted tile of the
-// prologue, whichever is larger, then the time-factor chunk, the restriction rows and a
-// copy of the stencil tables.
+// prologue, whichever is larger, then the time-factor chunk, the restriction rows, a
+// copy of the stencil tables and the edge data of each patch slot.
 __host__ __device__ inline size_t burst_lds_bytes(int precision, int R, int C, int xch,
                                                   int threads, int ppb, int mx, int me,
                                                   int ns) {
@@ -167,7 +169,7 @@ __host__ __device__ inline size_t burst_lds_bytes(int precision, int R, int C, i
   const size_t region = ((exch > lift ? exch : lift) + 15) & ~size_t(15);
   const int TCH = 256;
   return region + (size_t)(ns > 0 ? ns : 1) * TCH * 8 + (size_t)ppb * me * 8 +
-         (size_t)tab_off(mx, me).size * 8 + 64;
+         (size_t)tab_off(mx, me).size * 8 + (size_t)ppb * 2 * (mx + me) * 8 + 64;
 }
 
 // ---------------------------------------------------------------- batched bursts

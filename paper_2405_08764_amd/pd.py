@@ -496,8 +496,8 @@ class Batch:
         return a.value, b.value
 
 
-BATCH_MENU = [(2, 1, 3), (2, 1, 5), (2, 1, 6), (2, 1, 7), (2, 2, 3), (1, 1, 5), (1, 1, 7),
-              (1, 2, 3)]  # (exchange, columns, rows) of the batch kernel's menu, by index
+BATCH_MENU = [(2, 1, 3), (2, 1, 5), (2, 1, 6), (2, 1, 7), (2, 2, 3), (1, 1, 5), (1, 2, 3),
+              (1, 3, 2), (1, 4, 2)]  # (exchange, columns, rows) of the batch kernel's menu
 
 
 N_FEAT, N_PARAMS = 33, 20993

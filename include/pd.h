@@ -207,7 +207,7 @@ pd_status pd_get_tables(pd_grid g, double* host_out);
 pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
 
 /* Options: PD_OPT_ALLOW_UNSTABLE (0/1) skips the stability guard; PD_OPT_ROWS_PER_LANE,
- * PD_OPT_COLS_PER_LANE (1..3), PD_OPT_PATCHES_PER_BLOCK, PD_OPT_BLOCK_THREADS (upper bound,
+ * PD_OPT_COLS_PER_LANE (1..4), PD_OPT_PATCHES_PER_BLOCK, PD_OPT_BLOCK_THREADS (upper bound,
  * 64..256) and PD_OPT_EXCHANGE (1 LDS, 2 in-wave, 3 hybrid) set the fused burst's launch shape
  * (0 = automatic).  Results do not depend on the launch shape (bitwise). */
 #define PD_OPT_ALLOW_UNSTABLE 1

@@ -221,6 +221,8 @@ bool next_shape(pd_grid g, int xch_only, bool split, std::vector<Shape>& out) {
           }
           if (burst_lds_bytes(g->d.precision, R, C, xch, threads, ppb, mx, me, g->src.ns) > 65536)
             continue;
+          // the prologue stages the stencil tables at TAB_STAGE values per team thread
+          if (tab_off(mx, me).size > TAB_STAGE * (xch == XCH_LANES ? 64 : threads)) continue;
           const double eff = (double)ppb * mx * me / ((double)threads * R * C);
           const double w = xch == XCH_LANES ? 1.5 : (xch == XCH_HYBRID ? 1.4 : 1.0);
           const double score = eff * w + 1e-3 * (C - 1) + 1e-4 * R - 1e-5 * threads;

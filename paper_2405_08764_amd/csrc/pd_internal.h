@@ -31,6 +31,13 @@ struct TabOff {
   int s_xi, s_eta, L_xe, L_ee, ew, c_xi, c_eta, scal, size;
 };
 
+// Stencil-table values each thread of a team stages in registers during the burst
+// prologue (the team copies at most TAB_STAGE * team threads values to LDS): with
+// m_xi, m_eta <= 64 the tables hold 5 (m_xi + m_eta) + 20 <= 660 values, and a 64-thread
+// team holds a patch only if ceil(m_xi / C) ceil(m_eta / R) <= 64 with C R <= 12, so
+// m_xi + m_eta <= 85 and at most 445 values; launch-shape choices check it anyway.
+constexpr int TAB_STAGE = 7;
+
 __host__ __device__ inline TabOff tab_off(int mx, int me) {
   TabOff t;
   t.s_xi = 0;

@@ -56,6 +56,19 @@ def cases():
         "ragged_13x7": W.problem(W.grid("identity", 9, 12, 13, 7, box=(0, 2.0, -1.0, 0.5)),
                                  W.config1()["fields"], W.config1()["bc"], W.config1()["src"],
                                  W.timing(2e-3, 5, 1)),
+        # two constant-in-time and two time-dependent source terms (every branch of the
+        # source handling in the burst prologue and the nano update)
+        "four_sources": W.problem(
+            W.grid("tanh", 9, 9, 9, 9, gparam=1.5, conv="upwind"),
+            W.config1()["fields"], W.config1()["bc"],
+            [(W.const(1.0), 0.5, ("cart", 1.0, ("sin", math.pi, 0.0), ("sin", math.pi, 0.0))),
+             (W.const(-0.7), 0.0, ("cart", 0.3, ("cos", 2 * math.pi, 0.0),
+                                   ("poly", 1.0, 0.5, 0.0, 0.0))),
+             (W.texp(1.0, -1.0), -1.0, ("cart", 1.0, ("sin", math.pi, 0.0),
+                                         ("sin", math.pi, 0.0))),
+             (W.tsin(1.0, 0.5, 3.0), 0.0, ("cart", 0.8, ("poly", 0.0, 1.0, -1.0, 0.0),
+                                           ("cos", math.pi, 0.25)))],
+            W.timing(2e-3, 5, 1)),
         "printed_c0_central": W.problem(
             W.grid("sine", 10, 10, 11, 11, gparam=0.3, conv="central", c0="printed"),
             W.config1()["fields"], W.config1()["bc"], W.config1()["src"], W.timing(2e-3, 5, 1)),

@@ -463,7 +463,7 @@ def main():
                      "issued_frac": issued_flops_per_update * per_step / kern_s / peak},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, steps_cap=50)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, steps_cap=1000)
     print(json.dumps(out), flush=True)
 
 

@@ -119,20 +119,24 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 
 // C[M][N] (ldc) = beta C + A B, A = M x K (row-major, or its transpose stored K x M when
 // ta), B = K x N (or N x K when tb).  64 x 64 tiles, 256 threads of 4 x 4 outputs.
+// Split K: block z sums k in [z kc, (z + 1) kc) into its own slice C + z * cz (the caller
+// reduces the slices in a fixed order); one slice (kc >= K, cz = 0) is the plain product.
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* __restrict__ A,
                                               int lda, int ta, const float* __restrict__ B,
                                               int ldb, int tb, float* __restrict__ C, int ldc,
-                                              float beta) {
+                                              float beta, int kc, long long cz) {
   __shared__ float As[16][65], Bs[16][65];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int kb = blockIdx.z * kc, ke = K < kb + kc ? K : kb + kc;
+  C += blockIdx.z * cz;
   float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     for (int e = threadIdx.x; e < 16 * 64; e += 256) {
       const int kk = e >> 6, mm = e & 63;
       const int gm = m0 + mm, gk = k0 + kk, gn = n0 + mm;
-      As[kk][mm] = (gm < M && gk < K) ? (ta ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk]) : 0.f;
-      Bs[kk][mm] = (gn < N && gk < K) ? (tb ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn]) : 0.f;
+      As[kk][mm] = (gm < M && gk < ke) ? (ta ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk]) : 0.f;
+      Bs[kk][mm] = (gn < N && gk < ke) ? (tb ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn]) : 0.f;
     }
     __syncthreads();
 #pragma unroll
@@ -159,6 +163,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
         *o = beta != 0.f ? beta * *o + acc[r][c] : acc[r][c];
       }
     }
+}
+
+// C[e] = sum over the S slices part[z][e], z ascending (n = M * N outputs, slices of n).
+__global__ void k_splitk_reduce(int n, int S, const float* __restrict__ part,
+                                float* __restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float acc = part[e];
+  for (int z = 1; z < S; ++z) acc += part[(long long)z * n + e];
+  C[e] = acc;
 }
 
 // H += bias (per column), A = GELU(H); n rows of CL_HID.
@@ -547,16 +561,31 @@ hipError_t launch_closure_features(const Geo& g, const SrcInfo& src, const doubl
 }
 
 // Workspace of one training step on a batch of nb rows: H1, A1, H2, A2, dH2 (reused as
-// dA1 / dH1) [nb][CL_HID], out, dout [nb], grad [CL_NPAR].
+// dA1 / dH1) [nb][CL_HID], out, dout [nb], grad [CL_NPAR], and CL_SPLITK slices of
+// CL_HID x CL_HID partial sums for the weight gradients (whose reduction runs over the nb
+// rows: split into up to CL_SPLITK chunks so that they fill the device).
 hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float* par,
                             float* H1, float* A1, float* H2, float* A2, float* dH2,
                             float* dH1, float* out, float* dout, float* grad, float* loss,
-                            hipStream_t s) {
+                            float* part, hipStream_t s) {
   const dim3 blk(256);
   auto gemm = [&](int M, int N, int K, const float* A, int lda, int ta, const float* B, int ldb,
                   int tb, float* C, int ldc) {
-    hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64), blk, 0, s, M, N, K, A, lda,
-                       ta, B, ldb, tb, C, ldc, 0.f);
+    hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, 1), blk, 0, s, M, N, K, A,
+                       lda, ta, B, ldb, tb, C, ldc, 0.f, K, 0ll);
+  };
+  // C (M x N, dense) = A^T B over the nb rows, in S slices of kc rows
+  auto gemm_tn_split = [&](int M, int N, const float* A, int lda, const float* B, int ldb,
+                           float* C) {
+    int S = (nb + 63) / 64;
+    if (S > CL_SPLITK) S = CL_SPLITK;
+    const int kc = (((nb + S - 1) / S) + 15) / 16 * 16;
+    S = (nb + kc - 1) / kc;
+    const long long n = (long long)M * N;
+    hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, S), blk, 0, s, M, N, nb, A,
+                       lda, 1, B, ldb, 0, part, N, 0.f, kc, n);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((n + 255) / 256)), blk, 0, s, (int)n, S,
+                       part, C);
   };
   const long long nh = (long long)nb * CL_HID;
   const unsigned eb = (unsigned)((nh + 255) / 256);
@@ -568,10 +597,10 @@ hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float
                      loss);
   if (!y) return hipGetLastError();
   // dW2 = A1^T dH2; dA1 = dH2 W2^T; dH1 = dA1 GELU'(H1); dW1 = Xn^T dH1
-  gemm(CL_HID, CL_HID, nb, A1, CL_HID, 1, dH2, CL_HID, 0, grad + CL_OW2, CL_HID);
+  gemm_tn_split(CL_HID, CL_HID, A1, CL_HID, dH2, CL_HID, grad + CL_OW2);
   gemm(nb, CL_HID, CL_HID, dH2, CL_HID, 0, par + CL_OW2, CL_HID, 1, dH1, CL_HID);
   hipLaunchKernelGGL(k_gelu_back, dim3(eb), blk, 0, s, nb, dH1, H1);
-  gemm(CL_FEAT, CL_HID, nb, Xn, CL_FEAT, 1, dH1, CL_HID, 0, grad + CL_OW1, CL_HID);
+  gemm_tn_split(CL_FEAT, CL_HID, Xn, CL_FEAT, dH1, CL_HID, grad + CL_OW1);
   hipLaunchKernelGGL(k_colsums, dim3(CL_HID + 1), blk, 0, s, nb, dH1, dH2, A2, dout, grad);
   return hipGetLastError();
 }

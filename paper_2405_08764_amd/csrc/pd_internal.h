@@ -258,6 +258,7 @@ constexpr int CL_OW1 = 0, CL_OB1 = CL_OW1 + CL_FEAT * CL_HID, CL_OW2 = CL_OB1 + 
 // per-patch static closure data (doubles): node i, j; rates a, b, c, d; phi; micro-to-macro
 // spacing ratios dxi/Dxi, deta/Deta; constant source at the centre; time-dependent source
 // parts at the centre (2)
+constexpr int CL_SPLITK = 64;  // row chunks of the weight-gradient products
 constexpr int CL_NST = 12;
 hipError_t launch_closure_static(const Geo& g, const SrcInfo& src, const int* pmap,
                                  const double* coef, long long plane, double* st,
@@ -292,7 +293,7 @@ hipError_t launch_closure_features(const Geo& g, const SrcInfo& src, const doubl
 hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float* par,
                             float* H1, float* A1, float* H2, float* A2, float* dH2,
                             float* dH1, float* out, float* dout, float* grad, float* loss,
-                            hipStream_t s);
+                            float* part, hipStream_t s);
 hipError_t launch_adam(float* par, float* m, float* v, const float* g, int step, float lr,
                        hipStream_t s);
 hipError_t launch_colstats(long long n, const float* X, float* mu, float* sd, hipStream_t s);

@@ -489,15 +489,22 @@ __global__ __launch_bounds__(256) void k_mlp_infer(long long n, const float* __r
 // block b takes item b = (instance, first patch) and the instance's tables, with the
 // macro step, buffers and Dirichlet values from the shared clock as in the batch kernel.
 
+// Closure macro step: each wave takes one unit of 64 patches (a batch item, or patches
+// 64 u .. 64 u + 63 of the single grid), gathers and standardises their inputs, the block
+// runs the network on its four 64-row tiles (MFMA), and each wave writes its patches'
+// projected values.
 __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
-  __shared__ __align__(16) unsigned short xt[64 * K1P];
+  __shared__ __align__(16) unsigned short xt[4 * 64 * K1P];
   __shared__ __align__(16) unsigned short ht[64 * CL_HID];
-  __shared__ float part[128], res[64];
-  __shared__ double sF0[64], sS[64], sU[64];
-  __shared__ int sNode[64];
+  __shared__ float part[128], res[4 * 64];
+  __shared__ double sF0[4 * 64], sS[4 * 64], sU[4 * 64];
+  __shared__ int sNode[4 * 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const bool batch = Cl.inst != nullptr;
-  const int inst = batch ? Cl.items[2 * blockIdx.x] : 0;
-  const long long p0 = batch ? Cl.items[2 * blockIdx.x + 1] : 64LL * blockIdx.x;
+  const int unit = blockIdx.x * 4 + w;
+  const bool valid = unit < Cl.n_items;
+  const int inst = batch && valid ? Cl.items[2 * unit] : 0;
+  const long long p0 = batch ? (valid ? Cl.items[2 * unit + 1] : 0) : 64LL * unit;
   const BurstArgs& A = batch ? Cl.inst[inst] : Cl.one;
   const double* st = batch ? Cl.st_tab[inst] : Cl.st_one;
   double* fhat = batch ? Cl.fhat_tab[inst] : Cl.fhat_one;
@@ -509,40 +516,42 @@ __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
     Uin = (n & 1) ? A.Unew : A.U;
     Uout = (n & 1) ? const_cast<double*>(A.U) : A.Unew;
     t_n = A.t_n + (double)n * A.dt_macro;
-    if (p0 == 0 && A.bvals != nullptr) {  // Dirichlet nodes at t_n + dt_macro
+    if (valid && p0 == 0 && A.bvals != nullptr) {  // Dirichlet nodes at t_n + dt_macro
       const double* bv = A.bvals + (long long)Cl.k * A.nb;
-      for (int q = threadIdx.x; q < A.nb; q += blockDim.x) {
+      for (int q = lane; q < A.nb; q += 64) {
         int i, j;
         boundary_node(A.g, q, i, j);
         Uout[j * A.g.n_xi + i] = bv[q];
       }
     }
   }
-  const int t = threadIdx.x;
-  if (t < 64) {
-    const long long p = p0 + t;
-    if (p < A.g.P) {
-      Feat f;
-      closure_features(A.g, A.src, st + p * CL_NST, Uin, t_n, f);
+  const int r = w * 64 + lane;
+  const long long p = p0 + lane;
+  const bool mine = valid && p < A.g.P;
+  unsigned short* xr = xt + r * K1P;
+  if (mine) {
+    Feat f;
+    closure_features(A.g, A.src, st + p * CL_NST, Uin, t_n, f);
 #pragma unroll
-      for (int q = 0; q < K1P; ++q)
-        xt[t * K1P + q] = q < CL_FEAT ? to_bf16((f.x[q] - Cl.mu[q]) / Cl.sd[q]) : (unsigned short)0;
-      sF0[t] = f.F0;
-      sS[t] = f.s;
-      sU[t] = f.u;
-      sNode[t] = f.node;
-    } else {
-      for (int q = 0; q < K1P; ++q) xt[t * K1P + q] = 0;
-    }
+    for (int q = 0; q < K1P; ++q)
+      xr[q] = q < CL_FEAT ? to_bf16((f.x[q] - Cl.mu[q]) / Cl.sd[q]) : (unsigned short)0;
+    sF0[r] = f.F0;
+    sS[r] = f.s;
+    sU[r] = f.u;
+    sNode[r] = f.node;
+  } else {
+    for (int q = 0; q < K1P; ++q) xr[q] = 0;
   }
   __syncthreads();
-  mlp_tile(Cl.W, xt, ht, part, res);
-  if (t < 64 && p0 + t < A.g.P) {
-    const double Fh = sF0[t] + sS[t] * ((double)Cl.ys[0] + (double)Cl.ys[1] * (double)res[t]);
-    const double un = sU[t] + A.dt_macro * Fh;
-    Uout[sNode[t]] = un;
-    if (fhat) fhat[p0 + t] = Fh;
-    if (batch && Cl.sres_tab) Cl.sres_tab[inst][p0 + t] = (float)sS[t];
+  for (int tile = 0; tile < 4; ++tile)  // uniform: tiles of units past the end are skipped
+    if (blockIdx.x * 4 + tile < Cl.n_items)
+      mlp_tile(Cl.W, xt + tile * 64 * K1P, ht, part, res + tile * 64);
+  if (mine) {
+    const double Fh = sF0[r] + sS[r] * ((double)Cl.ys[0] + (double)Cl.ys[1] * (double)res[r]);
+    const double un = sU[r] + A.dt_macro * Fh;
+    Uout[sNode[r]] = un;
+    if (fhat) fhat[p] = Fh;
+    if (batch && Cl.sres_tab) Cl.sres_tab[inst][p] = (float)sS[r];
     if (!isfinite(un)) atomicOr(A.flag, 1);
   }
 }
@@ -647,8 +656,8 @@ hipError_t launch_mlp_infer(long long n, const float* Xn, const unsigned short* 
   return hipGetLastError();
 }
 
-hipError_t launch_closure_step(const ClosureArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_closure_step, dim3(blocks), dim3(256), 0, s, a);
+hipError_t launch_closure_step(const ClosureArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_closure_step, dim3((a.n_items + 3) / 4), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

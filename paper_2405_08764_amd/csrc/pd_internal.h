@@ -278,7 +278,7 @@ struct ClosureArgs {
   const double* const* st_tab;    // batch: per-instance static closure data
   double* const* fhat_tab;        // batch: per-instance F_hat
   const int* items;               // batch: (instance, first patch) pairs
-  int n_items;
+  int n_items;                    // units of 64 patches (batch items, or ceil(P / 64))
   int k;                          // batch: step within the graph replay
   float* const* sres_tab;         // batch: per-instance closure scale s (spot residuals)
   MlpW W;
@@ -306,6 +306,6 @@ hipError_t launch_pack(const float* par, unsigned short* w1t, unsigned short* w2
 hipError_t launch_mlp_infer(long long n, const float* Xn, const unsigned short* w1t,
                             const unsigned short* w2t, const unsigned short* w3, const float* par,
                             float* out, hipStream_t s);
-hipError_t launch_closure_step(const ClosureArgs& a, int blocks, hipStream_t s);
+hipError_t launch_closure_step(const ClosureArgs& a, hipStream_t s);
 
 }  // namespace pdk

@@ -95,11 +95,36 @@ __device__ inline int item_patches(const BatchItem& I) {
   }
 }
 
+// Exclusive prefix sum over one block of SEG_THREADS threads: v is this thread's value;
+// returns the sum of the values of the threads before it and sets total.
+constexpr int SEG_THREADS = 256;
+__device__ int block_exclusive_scan(int v, int* scratch, int& total) {
+  const int t = threadIdx.x;
+  scratch[t] = v;
+  __syncthreads();
+  for (int o = 1; o < SEG_THREADS; o <<= 1) {  // Hillis-Steele inclusive scan
+    const int x = t >= o ? scratch[t - o] : 0;
+    __syncthreads();
+    scratch[t] += x;
+    __syncthreads();
+  }
+  total = scratch[SEG_THREADS - 1];
+  const int incl = scratch[t];
+  __syncthreads();
+  return incl - v;
+}
+
 // One block: this step's spot-check segments (per instance, every stride-th item from a
 // hashed offset, at least one item), their prefix sums and total; clears the residuals.
-__global__ void k_spot_segments(SpotArgs S) {
+// Each thread takes a contiguous run of instances, so the prefix order is the instance
+// order.
+__global__ __launch_bounds__(SEG_THREADS) void k_spot_segments(SpotArgs S) {
+  __shared__ int scan[SEG_THREADS];
   const long long step = S.clk->base + S.k;
-  for (int i = threadIdx.x; i < S.n; i += blockDim.x) {
+  const int per = (S.n + SEG_THREADS - 1) / SEG_THREADS;
+  const int i0 = threadIdx.x * per, i1 = i0 + per < S.n ? i0 + per : S.n;
+  int mine = 0;
+  for (int i = i0; i < i1; ++i) {
     const int cnt = S.count[i];
     unsigned int h = (unsigned int)(step * 2654435761ull) ^ (unsigned int)(i * 40503u + 17u);
     h ^= h >> 15;
@@ -114,16 +139,15 @@ __global__ void k_spot_segments(SpotArgs S) {
     }
     S.spot[i] = make_int4(S.first[i] + f, c, S.stride, 0);
     S.resid[i] = 0u;
+    mine += c;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {  // sequential prefix (a few hundred instances)
-    int run = 0;
-    for (int i = 0; i < S.n; ++i) {
-      S.spot[i].w = run;
-      run += S.spot[i].y;
-    }
-    *S.spot_n = run;
+  int total;
+  int run = block_exclusive_scan(mine, scan, total);
+  for (int i = i0; i < i1; ++i) {
+    S.spot[i].w = run;
+    run += S.spot[i].y;
   }
+  if (threadIdx.x == 0) *S.spot_n = total;
 }
 
 // Residuals of the checked patches: |F_hat - F| / s with F from the plain step just
@@ -162,29 +186,42 @@ __global__ void k_spot_residuals(SpotArgs S, const BurstArgs* __restrict__ inst,
 
 // One block: fallback segments (every item of each instance whose residual exceeds the
 // threshold) and their count.
-__global__ void k_redo_segments(SpotArgs S) {
-  if (threadIdx.x != 0) return;
-  int run = 0, bad = 0;
-  for (int i = 0; i < S.n; ++i) {
+__global__ __launch_bounds__(SEG_THREADS) void k_redo_segments(SpotArgs S) {
+  __shared__ int scan[SEG_THREADS];
+  const int per = (S.n + SEG_THREADS - 1) / SEG_THREADS;
+  const int i0 = threadIdx.x * per, i1 = i0 + per < S.n ? i0 + per : S.n;
+  int mine = 0, bad = 0;
+  for (int i = i0; i < i1; ++i) {
+    const float r = __uint_as_float(S.resid[i]);
+    const bool redo = !((double)r <= S.threshold);
+    mine += redo ? S.count[i] : 0;
+    bad += redo ? 1 : 0;
+  }
+  int total;
+  int run = block_exclusive_scan(mine, scan, total);
+  int nbad;
+  (void)block_exclusive_scan(bad, scan, nbad);
+  for (int i = i0; i < i1; ++i) {
     const float r = __uint_as_float(S.resid[i]);
     const bool redo = !((double)r <= S.threshold);
     S.redo[i] = make_int4(S.first[i], redo ? S.count[i] : 0, 1, run);
     run += redo ? S.count[i] : 0;
-    bad += redo ? 1 : 0;
   }
-  *S.redo_n = run;
-  if (bad) atomicAdd(&S.stats[1], (unsigned long long)bad);
+  if (threadIdx.x == 0) {
+    *S.redo_n = total;
+    if (nbad) atomicAdd(&S.stats[1], (unsigned long long)nbad);
+  }
 }
 
 }  // namespace
 
 hipError_t launch_spot_segments(const SpotArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_spot_segments, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_spot_segments, dim3(1), dim3(SEG_THREADS), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_redo_segments(const SpotArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_redo_segments, dim3(1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_redo_segments, dim3(1), dim3(SEG_THREADS), 0, s, a);
   return hipGetLastError();
 }
 

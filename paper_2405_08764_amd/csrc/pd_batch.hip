@@ -23,6 +23,12 @@ __device__ __forceinline__ void run_item(const BurstArgs& A, const BatchItem& I,
         ~size_t(15);
     const LdsMap M = lds_map<double, R, C, NSB>(A, L, smem + w * slice, 1);
     body_x<double, R, C, NSB, MODE_FUSED>(A, L, M, Uin, Uout, ttab);
+  } else if constexpr (XCH == XCH_HYBRID) {
+    const LaneMap L = lane_map_h<R, C>(A, threadIdx.x, BATCH_THREADS, I.p0, I.ppb);
+    const int nbt = BATCH_WAVES * (64 / L.Lb);
+    const LdsMap M =
+        lds_map<double, R, C, NSB>(A, L, smem, 1, hybrid_edge_bytes(8, C, L.Lb, nbt));
+    body_h<double, R, C, NSB, MODE_FUSED>(A, L, M, Uin, Uout, ttab, nbt);
   } else {
     const LaneMap L = lane_map<R, C>(A, threadIdx.x, BATCH_THREADS, I.p0, I.ppb);
     const LdsMap M = lds_map<double, R, C, NSB>(A, L, smem, 2);

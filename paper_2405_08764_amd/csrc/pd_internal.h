@@ -181,13 +181,13 @@ __host__ __device__ inline size_t burst_lds_bytes(int precision, int R, int C, i
 
 // ---------------------------------------------------------------- batched bursts
 // Launch shapes the persistent batch kernel can run: (id, exchange, columns, rows per
-// lane).  In-wave shapes run four single-wave teams per block; LDS shapes one team of
-// the whole block.
+// lane).  In-wave shapes run four single-wave teams per block; LDS and hybrid shapes one
+// team of the whole block.
 #define PD_BATCH_MENU(X)                                                                 \
   X(0, XCH_LANES, 1, 3) X(1, XCH_LANES, 1, 5) X(2, XCH_LANES, 1, 6) X(3, XCH_LANES, 1, 7) \
   X(4, XCH_LANES, 2, 3) X(5, XCH_LDS, 1, 5) X(6, XCH_LDS, 2, 3) X(7, XCH_LDS, 3, 2)       \
-  X(8, XCH_LDS, 4, 2)
-constexpr int BATCH_MENU = 9;
+  X(8, XCH_LDS, 4, 2) X(9, XCH_HYBRID, 2, 4)
+constexpr int BATCH_MENU = 10;
 constexpr int BATCH_THREADS = 256;
 constexpr int BATCH_WAVES = BATCH_THREADS / 64;
 

@@ -186,8 +186,9 @@ __host__ __device__ inline size_t burst_lds_bytes(int precision, int R, int C, i
 #define PD_BATCH_MENU(X)                                                                 \
   X(0, XCH_LANES, 1, 3) X(1, XCH_LANES, 1, 5) X(2, XCH_LANES, 1, 6) X(3, XCH_LANES, 1, 7) \
   X(4, XCH_LANES, 2, 3) X(5, XCH_LDS, 1, 5) X(6, XCH_LDS, 2, 3) X(7, XCH_LDS, 3, 2)       \
-  X(8, XCH_LDS, 4, 2) X(9, XCH_HYBRID, 2, 4)
-constexpr int BATCH_MENU = 10;
+  X(8, XCH_LDS, 4, 2) X(9, XCH_HYBRID, 2, 4) X(10, XCH_HYBRID, 3, 2)                     \
+  X(11, XCH_HYBRID, 2, 3)
+constexpr int BATCH_MENU = 12;
 constexpr int BATCH_THREADS = 256;
 constexpr int BATCH_WAVES = BATCH_THREADS / 64;
 

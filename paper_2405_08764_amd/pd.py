@@ -497,7 +497,8 @@ class Batch:
 
 
 BATCH_MENU = [(2, 1, 3), (2, 1, 5), (2, 1, 6), (2, 1, 7), (2, 2, 3), (1, 1, 5), (1, 2, 3),
-              (1, 3, 2), (1, 4, 2), (3, 2, 4)]  # (exchange, columns, rows) of the batch menu
+              (1, 3, 2), (1, 4, 2), (3, 2, 4), (3, 3, 2),
+              (3, 2, 3)]  # (exchange, columns, rows) of the batch kernel's menu, by index
 
 
 N_FEAT, N_PARAMS = 33, 20993

@@ -47,7 +47,7 @@ def run_single(pd, probs, U0, n_steps):
 
 @pytest.mark.parametrize("n_steps", [5, 21])
 def test_batch_equals_single_grids_bitwise_on_every_menu_shape(pd, n_steps):
-    probs = instances(pd, 12, n_steps)
+    probs = instances(pd, 14, n_steps)
     say("members", [(p["grid"]["geometry"], p["grid"]["n_xi"], p["grid"]["m_xi"],
                      p["time"]["n_t"]) for p in probs])
     grids = [pd.Grid(p) for p in probs]

@@ -186,30 +186,52 @@ __global__ void k_bias_gelu(int n, float* __restrict__ H, const float* __restric
 }
 
 // Output head: out = A2 w3 + b3, r = out - y, dout = 2 r / n, and per-row products for
-// the gradients; dH2 = dout w3 GELU'(H2).  One block of CL_HID threads per row.
-__global__ void k_head(int n, const float* __restrict__ A2, const float* __restrict__ H2,
-                       const float* __restrict__ par, const float* __restrict__ y,
-                       float* __restrict__ out, float* __restrict__ dout,
-                       float* __restrict__ dH2, float* __restrict__ loss) {
-  __shared__ float red[CL_HID];
-  const int r = blockIdx.x, c = threadIdx.x;
+// the gradients; dH2 = dout w3 GELU'(H2).  One wave per row (two columns per lane, a
+// cross-lane sum), HEAD_ROWS rows per block; the block adds its rows' squared residuals
+// to the loss with one atomic.
+constexpr int HEAD_ROWS = 4;
+__global__ __launch_bounds__(64 * HEAD_ROWS) void k_head(int n, const float* __restrict__ A2,
+                                                         const float* __restrict__ H2,
+                                                         const float* __restrict__ par,
+                                                         const float* __restrict__ y,
+                                                         float* __restrict__ out,
+                                                         float* __restrict__ dout,
+                                                         float* __restrict__ dH2,
+                                                         float* __restrict__ loss) {
+  __shared__ float lsum[HEAD_ROWS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r = blockIdx.x * HEAD_ROWS + w;
   const float* w3 = par + CL_OW3;
-  red[c] = A2[(long long)r * CL_HID + c] * w3[c];
-  __syncthreads();
-  for (int w = CL_HID / 2; w > 0; w >>= 1) {
-    if (c < w) red[c] += red[c + w];
-    __syncthreads();
-  }
-  const float o = red[0] + par[CL_OB3];
-  if (out && c == 0) out[r] = o;
-  if (y) {
-    const float res = o - y[r];
-    const float d = 2.0f * res / (float)n;
-    if (c == 0) {
-      dout[r] = d;
-      atomicAdd(loss, res * res / (float)n);
+  float o = 0.f, sq = 0.f;
+  if (r < n) {
+    float v = 0.f;
+#pragma unroll
+    for (int h = 0; h < CL_HID / 64; ++h) {
+      const int c = lane + 64 * h;
+      v += A2[(long long)r * CL_HID + c] * w3[c];
     }
-    dH2[(long long)r * CL_HID + c] = d * w3[c] * gelu_grad_f(H2[(long long)r * CL_HID + c]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    o = v + par[CL_OB3];
+    if (out && lane == 0) out[r] = o;
+    if (y) {
+      const float res = o - y[r];
+      const float d = 2.0f * res / (float)n;
+      if (lane == 0) dout[r] = d;
+      sq = res * res / (float)n;
+#pragma unroll
+      for (int h = 0; h < CL_HID / 64; ++h) {
+        const int c = lane + 64 * h;
+        dH2[(long long)r * CL_HID + c] = d * w3[c] * gelu_grad_f(H2[(long long)r * CL_HID + c]);
+      }
+    }
+  }
+  if (lane == 0) lsum[w] = sq;
+  __syncthreads();
+  if (y && threadIdx.x == 0) {
+    float t = 0.f;
+    for (int k = 0; k < HEAD_ROWS; ++k) t += lsum[k];
+    atomicAdd(loss, t);
   }
 }
 
@@ -602,8 +624,8 @@ hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float
   hipLaunchKernelGGL(k_bias_gelu, dim3(eb), blk, 0, s, nb, H1, par + CL_OB1, A1);
   gemm(nb, CL_HID, CL_HID, A1, CL_HID, 0, par + CL_OW2, CL_HID, 0, H2, CL_HID);
   hipLaunchKernelGGL(k_bias_gelu, dim3(eb), blk, 0, s, nb, H2, par + CL_OB2, A2);
-  hipLaunchKernelGGL(k_head, dim3(nb), dim3(CL_HID), 0, s, nb, A2, H2, par, y, out, dout, dH2,
-                     loss);
+  hipLaunchKernelGGL(k_head, dim3((nb + HEAD_ROWS - 1) / HEAD_ROWS), dim3(64 * HEAD_ROWS), 0, s,
+                     nb, A2, H2, par, y, out, dout, dH2, loss);
   if (!y) return hipGetLastError();
   // dW2 = A1^T dH2; dA1 = dH2 W2^T; dH1 = dA1 GELU'(H1); dW1 = Xn^T dH1
   gemm_tn_split(CL_HID, CL_HID, A1, CL_HID, dH2, CL_HID, grad + CL_OW2);

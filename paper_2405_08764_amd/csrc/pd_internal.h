@@ -168,8 +168,8 @@ __host__ __device__ inline size_t burst_lds_bytes(int precision, int R, int C, i
   const int Lb = (mx + C - 1) / C;
   const size_t nbuf = xch == XCH_LDS ? 2 : 1;
   size_t exch = nbuf * R * C * (size_t)(threads + 2 * (Lb + 1)) * rs;
-  if (xch == XCH_HYBRID) {  // band-edge planes: 2 buffers x (top, bottom) x (bands + 2)
-    const size_t edges = (size_t)4 * ((threads / 64) * (64 / Lb) + 2) * C * Lb * rs;
+  if (xch == XCH_HYBRID) {  // band-edge planes: 2 buffers x (top, bottom) x (bands + 3)
+    const size_t edges = (size_t)4 * ((threads / 64) * (64 / Lb) + 3) * C * Lb * rs;
     if (edges > exch) exch = edges;
   }
   const size_t lift = (size_t)ppb * (mx + 2) * (me + 2) * 8;

@@ -36,8 +36,14 @@ __device__ __forceinline__ void run_item(const BurstArgs& A, const BatchItem& I,
   }
 }
 
+// Three blocks per CU (12 waves, at most 168 registers per lane): the multi-wave teams
+// wait on LDS round trips and a barrier every nano step, and a third wave per SIMD hides
+// much of that (measured on the mixed batch: 357 -> 315 ms per step; the in-wave shapes
+// run as fast as at two waves per SIMD).  Shapes that no longer fit in registers spill
+// (the LDS exchange with four columns per lane doubles its time) and lose in the
+// autotuner; a fourth wave per SIMD (128 registers) spills everywhere.
 template <int NSB>
-__global__ __launch_bounds__(BATCH_THREADS) void k_batch(BatchArgs B) {
+__global__ __launch_bounds__(BATCH_THREADS, 3) void k_batch(BatchArgs B) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_item;
   for (;;) {

@@ -19,7 +19,10 @@
  *   macro step        closed-form 9-point macro stencil for constant diffusion (any n_t)
  *   whole scheme      manufactured-solution convergence on square and annulus; the
  *                     Fourier-Bessel series of Sec. 4.2 (ballpark of Table P2_PerErr)
- *   full domain       independent brute-force lattice solver in the tests
+ *   full domain       quadratic (central) and linear (upwind) steady states with the
+ *                     manufactured source; constants kept on a mapped box;
+ *                     manufactured convergence (central order 2, upwind order 1);
+ *                     it is also the brute-force reference patch dynamics converges to
  * The readings taken where the paper is silent are listed where they are used.
  */
 #include "pdo.h"
@@ -818,55 +821,74 @@ double pdo_dt_macro_limit(const pdo_grid* g, const pdo_problem* pr) {
 }
 
 /* ---------------------------------------------------- full-domain explicit run ---- */
+/* The operator of eq. (Computational_Problem) on one lattice over the whole box, with the
+ * micro differences of a burst (3-point second differences; 2-point upwind or central
+ * first differences) and forward Euler; the boundary rows (and columns unless xi is
+ * periodic) take the Dirichlet data u_b at the end of each step. */
+
+static void fd_spacing(const pdo_grid* g, int n_x, int n_y, double* hx, double* hy) {
+  *hx = g->periodic_xi ? (g->xi1 - g->xi0) / n_x : (g->xi1 - g->xi0) / (n_x - 1);
+  *hy = (g->eta1 - g->eta0) / (n_y - 1);
+}
+
+static int fd_is_boundary(const pdo_grid* g, int n_x, int n_y, int i, int j) {
+  return (j == 0 || j == n_y - 1) || (!g->periodic_xi && (i == 0 || i == n_x - 1));
+}
+
+/* Forward-Euler update of interior node (i, j) from U at time t: c are the operator's
+ * coefficients and source parts at the node, T the source time factors at t. */
+static double fd_update(const pdo_grid* g, const pdo_problem* pr, const double* c,
+                        const double* T, const double* U, int n_x, double hx, double hy,
+                        int i, int j, double dt) {
+  int iw = i - 1 < 0 ? n_x - 1 : i - 1, ie = i + 1 >= n_x ? 0 : i + 1;
+  double uc = U[j * n_x + i], uW = U[j * n_x + iw], uE = U[j * n_x + ie];
+  double uS = U[(j - 1) * n_x + i], uN = U[(j + 1) * n_x + i];
+  double dxx = (uE - 2.0 * uc + uW) / (hx * hx);
+  double dee = (uN - 2.0 * uc + uS) / (hy * hy);
+  double dx1, de1;
+  if (g->conv == PDO_CONV_CENTRAL) {
+    dx1 = (uE - uW) / (2.0 * hx);
+    de1 = (uN - uS) / (2.0 * hy);
+  } else {
+    dx1 = c[2] >= 0.0 ? (uc - uW) / hx : (uE - uc) / hx;
+    de1 = c[3] >= 0.0 ? (uc - uS) / hy : (uN - uc) / hy;
+  }
+  double src = 0.0;
+  for (int q = 0; q < pr->n_src; ++q) src += T[q] * c[5 + q];
+  double rhs = c[0] * dxx + c[1] * dee - c[2] * dx1 - c[3] * de1 + c[4] * uc + src;
+  return uc + dt * rhs;
+}
 
 int pdo_full_domain(const pdo_grid* g, const pdo_problem* pr, int n_x, int n_y, double* U,
                     double t0, double dt, int n_steps) {
   if (n_x < 3 || n_y < 3) return PDO_EINVAL;
-  double hx = g->periodic_xi ? (g->xi1 - g->xi0) / n_x : (g->xi1 - g->xi0) / (n_x - 1);
-  double hy = (g->eta1 - g->eta0) / (n_y - 1);
+  double hx, hy;
+  fd_spacing(g, n_x, n_y, &hx, &hy);
   int nc = PDO_NCOEF(pr);
   size_t n = (size_t)n_x * n_y;
   double* C = (double*)malloc(n * nc * sizeof(double));
   double* V = (double*)malloc(n * sizeof(double));
-  double out[5 + PDO_MAXTERM];
-  for (int j = 0; j < n_y; ++j)
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < n_y; ++j) {
+    double out[5 + PDO_MAXTERM];
     for (int i = 0; i < n_x; ++i) {
       pdo_coeffs_at(g, pr, g->xi0 + i * hx, g->eta0 + j * hy, out);
       for (int q = 0; q < nc; ++q) C[((size_t)j * n_x + i) * nc + q] = out[q];
     }
+  }
   int rc = PDO_OK;
   for (int s = 0; s < n_steps; ++s) {
     double t = t0 + s * dt;
     double T[PDO_MAXTERM];
     for (int q = 0; q < pr->n_src; ++q) T[q] = tfun_eval(&pr->src_t[q], t);
-    memcpy(V, U, n * sizeof(double));
-    for (int j = 1; j < n_y - 1; ++j)
-      for (int i = 0; i < n_x; ++i) {
-        if (!g->periodic_xi && (i == 0 || i == n_x - 1)) continue;
-        int iw = i - 1 < 0 ? n_x - 1 : i - 1, ie = i + 1 >= n_x ? 0 : i + 1;
-        const double* c = C + ((size_t)j * n_x + i) * nc;
-        double uc = U[j * n_x + i], uW = U[j * n_x + iw], uE = U[j * n_x + ie];
-        double uS = U[(j - 1) * n_x + i], uN = U[(j + 1) * n_x + i];
-        double dxx = (uE - 2.0 * uc + uW) / (hx * hx);
-        double dee = (uN - 2.0 * uc + uS) / (hy * hy);
-        double dx1, de1;
-        if (g->conv == PDO_CONV_CENTRAL) {
-          dx1 = (uE - uW) / (2.0 * hx);
-          de1 = (uN - uS) / (2.0 * hy);
-        } else {
-          dx1 = c[2] >= 0.0 ? (uc - uW) / hx : (uE - uc) / hx;
-          de1 = c[3] >= 0.0 ? (uc - uS) / hy : (uN - uc) / hy;
-        }
-        double src = 0.0;
-        for (int q = 0; q < pr->n_src; ++q) src += T[q] * c[5 + q];
-        double rhs = c[0] * dxx + c[1] * dee - c[2] * dx1 - c[3] * de1 + c[4] * uc + src;
-        V[j * n_x + i] = uc + dt * rhs;
-      }
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < n_y; ++j)
       for (int i = 0; i < n_x; ++i) {
-        int bnd = (j == 0 || j == n_y - 1) || (!g->periodic_xi && (i == 0 || i == n_x - 1));
-        if (bnd) V[j * n_x + i] = pdo_boundary_value(g, pr, g->xi0 + i * hx, g->eta0 + j * hy,
-                                                     t + dt);
+        if (fd_is_boundary(g, n_x, n_y, i, j))
+          V[j * n_x + i] = pdo_boundary_value(g, pr, g->xi0 + i * hx, g->eta0 + j * hy, t + dt);
+        else
+          V[j * n_x + i] = fd_update(g, pr, C + ((size_t)j * n_x + i) * nc, T, U, n_x, hx, hy,
+                                     i, j, dt);
       }
     memcpy(U, V, n * sizeof(double));
     for (size_t q = 0; q < n; ++q)
@@ -876,4 +898,16 @@ int pdo_full_domain(const pdo_grid* g, const pdo_problem* pr, int n_x, int n_y, 
   free(C);
   free(V);
   return rc;
+}
+
+double pdo_full_domain_point(const pdo_grid* g, const pdo_problem* pr, int n_x, int n_y,
+                             const double* U, double t, double dt, int i, int j) {
+  double hx, hy;
+  fd_spacing(g, n_x, n_y, &hx, &hy);
+  if (fd_is_boundary(g, n_x, n_y, i, j))
+    return pdo_boundary_value(g, pr, g->xi0 + i * hx, g->eta0 + j * hy, t + dt);
+  double c[5 + PDO_MAXTERM], T[PDO_MAXTERM];
+  pdo_coeffs_at(g, pr, g->xi0 + i * hx, g->eta0 + j * hy, c);
+  for (int q = 0; q < pr->n_src; ++q) T[q] = tfun_eval(&pr->src_t[q], t);
+  return fd_update(g, pr, c, T, U, n_x, hx, hy, i, j, dt);
 }

@@ -157,6 +157,10 @@ double pdo_dt_macro_limit(const pdo_grid* g, const pdo_problem* prob);
  * lattice points including the boundary, U in/out [n_y][n_x]. */
 int pdo_full_domain(const pdo_grid* g, const pdo_problem* prob, int n_x, int n_y, double* U,
                     double t0, double dt, int n_steps);
+/* The value one step of pdo_full_domain from time t gives at node (i, j) alone (the
+ * Dirichlet value at t + dt on a boundary node): spot checks of large lattices. */
+double pdo_full_domain_point(const pdo_grid* g, const pdo_problem* prob, int n_x, int n_y,
+                             const double* U, double t, double dt, int i, int j);
 
 void pdo_set_threads(int n);
 int pdo_get_threads(void);

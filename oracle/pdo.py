@@ -7,6 +7,7 @@ library: its structures mirror ``pdo.h`` only.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import time
@@ -114,6 +115,8 @@ def lib(extended=False):
             "pdo_dt_macro_limit": (C.c_double, [GP, PP]),
             "pdo_full_domain": (C.c_int, [GP, PP, C.c_int, C.c_int, _DP, C.c_double,
                                           C.c_double, C.c_int]),
+            "pdo_full_domain_point": (C.c_double, [GP, PP, C.c_int, C.c_int, _DP, C.c_double,
+                                                   C.c_double, C.c_int, C.c_int]),
             "pdo_set_threads": (None, [C.c_int]),
             "pdo_get_threads": (C.c_int, []),
         }
@@ -330,6 +333,26 @@ class Oracle:
         if rc != 0:
             raise FloatingPointError("oracle full-domain status %d" % rc)
         return U
+
+    def full_domain_point(self, n_x, n_y, U, t, dt, i, j):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        return self.L.pdo_full_domain_point(self.G, self.Pp, int(n_x), int(n_y), _dp(U),
+                                            float(t), float(dt), int(i), int(j))
+
+    def full_domain_limit(self, n_x, n_y):
+        """Explicit forward-Euler bound over the lattice nodes (the same 5-point bound as
+        the micro limit, at the lattice spacing)."""
+        gd = self.prob["grid"]
+        hx = (gd["xi1"] - gd["xi0"]) / (n_x if gd["periodic_xi"] else n_x - 1)
+        hy = (gd["eta1"] - gd["eta0"]) / (n_y - 1)
+        lim = math.inf
+        for j in range(n_y):
+            for i in range(n_x):
+                c = self.coeffs_at(gd["xi0"] + i * hx, gd["eta0"] + j * hy)
+                b = 1.0 / (2 * c[0] / hx ** 2 + 2 * c[1] / hy ** 2 + abs(c[2]) / hx
+                           + abs(c[3]) / hy + abs(c[4]))
+                lim = min(lim, b)
+        return lim
 
     # -- helpers
     def node_coords(self):

@@ -39,12 +39,15 @@ BURST_SOURCES = ["pd_burst.inc", "pd_internal.h", "pd_burst_x_f64.hip", "pd_burs
                  "pd_burst_h_f32.hip"]
 
 
-def burst_source_hash():
-    """SHA-256 over the burst kernels' sources: a traffic figure taken from counters is
-    valid only for the code it was measured on."""
+FD_SOURCES = ["pd_fd.hip", "pd_internal.h"]
+
+
+def burst_source_hash(files=None):
+    """SHA-256 over a kernel's sources (default: the burst kernels'): a traffic figure
+    taken from counters is valid only for the code it was measured on."""
     import hashlib
     h = hashlib.sha256()
-    for f in BURST_SOURCES:
+    for f in (BURST_SOURCES if files is None else files):
         with open(os.path.join(ROOT, "paper_2405_08764_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -54,7 +57,7 @@ def traffic_file(kernel, workload, precision):
     return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_hbm_traffic.txt")
 
 
-def read_traffic(kernel, workload, precision, shape):
+def read_traffic(kernel, workload, precision, shape, files=None):
     """HBM bytes per launch from the committed counter summary, or None when there is
     none for this kernel, workload and launch shape, or the kernel changed since."""
     path = traffic_file(kernel, workload, precision)
@@ -66,13 +69,13 @@ def read_traffic(kernel, workload, precision, shape):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != burst_source_hash() or kv.get("shape") != shape:
+    if kv.get("source_sha256") != burst_source_hash(files) or kv.get("shape") != shape:
         return None
     return float(kv["hbm_bytes_per_launch"])
 
 
 def pmc_summary(fetch_csv, write_csv, kernel_prefix, calib_mib, out, command, workload,
-                precision, shape):
+                precision, shape, files=None):
     """Per-launch HBM traffic of a kernel from two rocprofv3 --pmc runs (FETCH_SIZE, then
     WRITE_SIZE, both in KiB per dispatch), each scaled by what the same counter reads for
     the calibration kernel of known traffic (calib_mib MiB read and written)."""
@@ -111,7 +114,7 @@ def pmc_summary(fetch_csv, write_csv, kernel_prefix, calib_mib, out, command, wo
         fh.write(f"fetch_raw_bytes_per_launch: {f_raw:.6e}\nfetch_scale: {ff:.4f}\n")
         fh.write(f"write_raw_bytes_per_launch: {w_raw:.6e}\nwrite_scale: {fw:.4f}\n")
         fh.write(f"hbm_bytes_per_launch: {total:.6e}\n")
-        fh.write(f"source_sha256: {burst_source_hash()}\n")
+        fh.write(f"source_sha256: {burst_source_hash(files)}\n")
     print(open(out).read())
 
 
@@ -303,6 +306,124 @@ def bench_closure(args):
     print(json.dumps(out), flush=True)
 
 
+def fd_cpu_baseline(prob, n, dt, steps):
+    """The FP64 CPU oracle's lattice solver on the same lattice (OpenMP over rows): a few
+    steps, the coefficient setup timed apart and excluded."""
+    import numpy as np
+    from oracle import pdo
+    threads = max(1, min(16, os.cpu_count() or 1))
+    o = pdo.Oracle(prob, threads=threads)
+    U = np.zeros((n, n))
+    s = time.perf_counter()
+    o.full_domain(n, n, U, 0.0, dt, 0)
+    t_setup = time.perf_counter() - s
+    s = time.perf_counter()
+    o.full_domain(n, n, U, 0.0, dt, steps)
+    el = time.perf_counter() - s - t_setup
+    interior = (n - 2) * (n - 2)
+    return {"value": interior * steps / el, "unit": "lattice updates/s",
+            "cores": o.L.pdo_get_threads(), "kind": "oracle",
+            "sample": f"{steps} steps of the {n}x{n} lattice, {el:.1f} s (coefficient setup "
+                      f"{t_setup:.1f} s excluded)"}
+
+
+def bench_full_domain(args):
+    """The full-domain explicit comparator (pd_fd_*): forward Euler with the bursts'
+    differences on one lattice over the whole box, for the config-2 problem; and the time
+    each method needs to reach the config-2 final time."""
+    import torch
+
+    from paper_2405_08764_amd import pd
+    from paper_2405_08764_amd import workloads as W
+    prob = W.config2()
+    n = args.fd_n
+    K = args.steps
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = pd.Grid(prob)
+        f = pd.FullDomain(g, n, n, frac=0.5)
+        info = f.query()
+        dt = info.dt
+        U = f.initial(0.0)
+        f.solve(U, 0.0, args.warmup)
+        f.sync()
+        U = f.initial(0.0)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s = time.perf_counter()
+        a.record(stream)
+        f.solve(U, 0.0, K)
+        b.record(stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - s
+        f.sync()
+        kern_s = a.elapsed_time(b) / 1e3 / K  # step kernels (+ one table pass per 256)
+        t_pd = None
+        if not args.fd_no_pd:
+            # patch dynamics on the same problem to the same final time, as the default
+            # config-2 benchmark runs it
+            gp = pd.Grid(prob)
+            Up = gp.initial()
+            gp.autotune(Up, reps=5)
+            gp.solve(Up, n_steps=32)
+            gp.sync()
+            Up = gp.initial()
+            torch.cuda.synchronize()
+            s = time.perf_counter()
+            gp.solve(Up, n_steps=prob["time"]["n_steps"])
+            torch.cuda.synchronize()
+            t_pd = time.perf_counter() - s
+            gp.sync()
+        if args.calibrate_copy:
+            # the streaming kernel of known traffic the counter summary is scaled by
+            m = args.calibrate_copy * (1 << 20) // 8
+            src = torch.ones(m, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(2):
+                torch.mul(src, 1.0, out=dst)
+            torch.cuda.synchronize()
+            del src, dst
+    ns = sum(1 for (tf, _, _) in prob["src"] if tf[0] != "const")
+    has_k = any(tf[0] == "const" for (tf, _, _) in prob["src"])
+    interior = (n - 2) * (n - 2)
+    nb = 4 * n - 4
+    planes = 5 + int(has_k) + ns
+    bytes_per_node = 8 * planes + 16  # weight planes and the field read once, one write
+    alg_bytes = interior * bytes_per_node + nb * 16
+    achieved = alg_bytes / kern_s
+    peak = 8.0e12
+    T_end = prob["time"]["n_steps"] * prob["time"]["dt_macro"]
+    fd_steps = math.ceil(T_end / dt)
+    traffic = read_traffic("k_fd_step", "full-domain", "f64", "fd", FD_SOURCES)
+    out = {
+        "metric": "lattice-point updates/s of the full-domain explicit comparator",
+        "value": interior * K / el,
+        "unit": "lattice updates/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": el / K * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded analytic coefficients, no dataset)",
+        "config": {"workload": f"full-domain: config-2 problem (tanh-stretched square, "
+                               f"beta 2.5, eps 1e-3, Fourier D and v, source (1 + sin 4 pi t) "
+                               f"g) on a {n}x{n} lattice, forward Euler at half the "
+                               f"explicit bound",
+                   "n": n, "dt": dt, "dt_limit": info.dt_limit,
+                   "spacing": info.spacing_x, "bytes_per_node_step": bytes_per_node},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": peak / 1e9,
+                     "unit": "GB/s", "frac": achieved / peak,
+                     "traffic": traffic, "algorithmic_bytes": alg_bytes,
+                     "kernel": "k_fd_step (one lattice step)", "kernel_ms": kern_s * 1e3},
+        "vs_patch_dynamics": {
+            "T": T_end, "fd_steps": fd_steps, "fd_time_s": fd_steps * el / K,
+            "pd_macro_steps": prob["time"]["n_steps"], "pd_time_s": t_pd,
+            "fd_over_pd_time": None if t_pd is None else fd_steps * el / K / t_pd,
+            "pd_micro_spacing": prob["grid"]["h_xi"] / (prob["grid"]["m_xi"] - 1)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = fd_cpu_baseline(prob, n, dt, args.fd_cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,7 +432,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=32)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config5"])
+                    choices=["config1", "config2", "config3", "config4", "config5",
+                             "full-domain"])
+    ap.add_argument("--fd-n", type=int, default=4097,
+                    help="full-domain: lattice nodes per side")
+    ap.add_argument("--fd-cpu-steps", type=int, default=200,
+                    help="full-domain: oracle steps of the CPU baseline")
+    ap.add_argument("--fd-no-pd", action="store_true",
+                    help="full-domain: skip the patch-dynamics run to the same final time")
     ap.add_argument("--train-instances", type=int, default=96,
                     help="config5: training instances (seeds disjoint from the batch)")
     ap.add_argument("--train-pairs", type=int, default=2_000_000,
@@ -339,8 +467,15 @@ def main():
     ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"config4": 10, "config5": 20}.get(args.workload, 1000)
+        args.steps = {"config4": 10, "config5": 20, "full-domain": 400}.get(args.workload,
+                                                                              1000)
     if args.pmc_summary:
+        if args.workload == "full-domain":
+            pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_fd_step",
+                        args.calibrate_copy or 256,
+                        traffic_file("k_fd_step", args.workload, "f64"), args.pmc_command,
+                        args.workload, "f64", "fd", FD_SOURCES)
+            return
         kernel = KERNEL_NAME[int(args.pmc_shape.split(",")[0])]
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], kernel + "<",
                     args.calibrate_copy or 256,
@@ -362,6 +497,8 @@ def main():
         return bench_batch(args)
     if args.workload == "config5":
         return bench_closure(args)
+    if args.workload == "full-domain":
+        return bench_full_domain(args)
     prob, desc = workload(args.workload)
     t = prob["time"]
     torch.cuda.set_device(0)

@@ -367,6 +367,48 @@ pd_status pd_batch_closure_solve(pd_batch b, int32_t n_steps, void* stream);
 pd_status pd_batch_closure_stats(pd_batch b, int64_t* checked, int64_t* fallbacks,
                                  int32_t reset);
 
+/* ------------------------------------------------------------ full-domain lattice
+ * The explicit comparator of the paper's full-domain solution (Sec. 4.1.2, Table
+ * PDvsFDS, there a method-of-lines run on one 151^2 lattice): the operator of
+ * eq. (Computational_Problem) of grid g's problem, discretised on one n_x x n_y lattice
+ * over the whole box with the bursts' differences (3-point second differences; 2-point
+ * upwind or central first differences, the grid's conv) and advanced by forward Euler
+ * steps of dt.  Lattice node (i, j) sits at (xi0 + i hx, eta0 + j hy) with
+ * hx = (xi1 - xi0) / (n_x - 1) (on a periodic xi axis (xi1 - xi0) / n_x, the nodes
+ * wrapping) and hy = (eta1 - eta0) / (n_y - 1); fields are FP64 row-major [n_y][n_x].
+ * After every step the boundary rows (and the end columns unless xi is periodic) take
+ * the Dirichlet data u_b at the step's end time; step s of a solve from t0 starts at
+ * t0 + s dt and its source time factors are taken there.
+ *  - pd_fd_create: host only; the grid must outlive the lattice.  PD_EINVAL for
+ *    n_x or n_y < 3 or more than 2^30 nodes.
+ *  - pd_fd_bind_workspace: caller device memory of workspace_bytes, 256-byte aligned
+ *    (PD_ENOMEM if smaller): weight planes, a second field buffer, step tables.
+ *  - pd_fd_prepare: folds the weights for dt (needs the grid's coefficients; do it again
+ *    after pd_set_coefficients) and computes the explicit bound over the lattice;
+ *    synchronises the stream once.  PD_EUNSTABLE if dt is above the bound (unless the
+ *    grid's PD_OPT_ALLOW_UNSTABLE is set), PD_EINVAL if diffusion is not positive.
+ *  - pd_fd_initial: U = u_b(t) at every lattice node (asynchronous).
+ *  - pd_fd_solve: n_steps >= 0 steps of U in place (asynchronous; PD_ESTATE before a
+ *    successful prepare).
+ *  - pd_fd_sync: synchronises and returns PD_ENONFINITE if a step produced a
+ *    non-finite value since the last sync. */
+typedef struct pd_fd_s* pd_fd;
+typedef struct {
+  int32_t n_x, n_y;
+  size_t workspace_bytes;
+  double dt_limit;             /* explicit bound over the lattice (after pd_fd_prepare) */
+  double dt;                   /* the prepared step (0 before pd_fd_prepare)            */
+  double spacing_x, spacing_y; /* hx, hy                                                */
+} pd_fd_info;
+pd_status pd_fd_create(pd_grid g, int32_t n_x, int32_t n_y, pd_fd* out);
+pd_status pd_fd_destroy(pd_fd f);
+pd_status pd_fd_query(pd_fd f, pd_fd_info* out);
+pd_status pd_fd_bind_workspace(pd_fd f, void* dev, size_t bytes);
+pd_status pd_fd_prepare(pd_fd f, double dt, void* stream);
+pd_status pd_fd_initial(pd_fd f, double* U, double t, void* stream);
+pd_status pd_fd_solve(pd_fd f, double* U, double t0, int32_t n_steps, void* stream);
+pd_status pd_fd_sync(pd_fd f, void* stream);
+
 const char* pd_last_error(void);
 
 #ifdef __cplusplus

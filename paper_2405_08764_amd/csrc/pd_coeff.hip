@@ -429,6 +429,95 @@ __global__ void k_clock_init(Clock* clk, double t0, double dt, double* b0, doubl
   }
 }
 
+// ------------------------------------------------------------ full-domain lattice
+// The lattice Geo: n_xi x n_eta nodes over the box with spacings Dxi, Deta (the box
+// divided into n_xi intervals when xi is periodic, n_xi - 1 otherwise).
+
+// Folded forward-Euler weights of every lattice node for the step dt: the operator of
+// eq. (Computational_Problem) with 3-point second differences and 2-point upwind (the
+// side the convection comes from) or central first differences, written as
+//   u' = cC u + cS u_S + cN u_N + cW u_W + cE u_E + K + sum_j T_j(t) sd_j,
+// cC = 1 + dt phi - (((E + W) + N) + S): the first-difference parts are differences of
+// neighbours, so the weights of a row sum to 1 + dt phi.  Planes [cC, cS, cN, cW, cE, K,
+// sd_0, sd_1] of `plane` doubles each; K holds the constant-in-time source terms.  Block
+// minima of the explicit bound (0 where diffusion is not positive) go to partial.
+__global__ void k_fd_weights(Geo g, const pd_coeff_desc* __restrict__ desc, SrcInfo src,
+                             int n_src, double dt, double* __restrict__ W, long long plane,
+                             double* __restrict__ partial) {
+  __shared__ double red[256];
+  double lim = INFINITY;
+  const double hx = g.Dxi, hy = g.Deta;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < plane;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(q / g.n_xi), i = (int)(q - (long long)j * g.n_xi);
+    double c[5 + PD_MAXTERM];
+    coefficients_at(g, *desc, n_src, g.xi0 + i * hx, g.eta0 + j * hy, c);
+    const double ax = c[0] / (hx * hx), ay = c[1] / (hy * hy);
+    double e, w, n, so;
+    if (g.conv == PD_CONV_CENTRAL) {
+      e = ax - c[2] / (2.0 * hx);
+      w = ax + c[2] / (2.0 * hx);
+      n = ay - c[3] / (2.0 * hy);
+      so = ay + c[3] / (2.0 * hy);
+    } else {
+      e = c[2] >= 0.0 ? ax : ax - c[2] / hx;
+      w = c[2] >= 0.0 ? ax + c[2] / hx : ax;
+      n = c[3] >= 0.0 ? ay : ay - c[3] / hy;
+      so = c[3] >= 0.0 ? ay + c[3] / hy : ay;
+    }
+    const double E = dt * e, Wt = dt * w, N = dt * n, S = dt * so;
+    W[q] = 1.0 + dt * c[4] - (((E + Wt) + N) + S);
+    W[plane + q] = S;
+    W[2 * plane + q] = N;
+    W[3 * plane + q] = Wt;
+    W[4 * plane + q] = E;
+    double K = 0.0;
+    for (int k = 0; k < src.nconst; ++k) K += src.ca[k] * c[src.plane_c[k]];
+    W[5 * plane + q] = dt * K;
+    for (int j2 = 0; j2 < src.ns; ++j2) W[(6 + j2) * plane + q] = dt * c[src.plane_t[j2]];
+    const double b = (c[0] > 0.0 && c[1] > 0.0)
+                         ? fe_bound(c[0], c[1], c[2], c[3], c[4], hx, hy)
+                         : 0.0;
+    lim = fmin(lim, b);
+  }
+  red[threadIdx.x] = lim;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_fd_limit_final(const double* __restrict__ partial, int nblocks,
+                                 double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double lim = INFINITY;
+  for (int b = 0; b < nblocks; ++b) lim = fmin(lim, partial[b]);
+  out[0] = lim;
+}
+
+// Time factors and Dirichlet data of lattice steps s0 .. s0 + S - 1 (S <= FD_CHUNK; step
+// s starts at t0 + s dt): ttab[j][k] = T_j(t0 + (s0 + k) dt) with rows of FD_CHUNK,
+// bvals[k][q] = u_b(node q) at the end of step s0 + k.
+__global__ void k_fd_tables(Geo g, SrcInfo src, const pd_coeff_desc* __restrict__ desc,
+                            double t0, double dt, long long s0, int S,
+                            double* __restrict__ ttab, double* __restrict__ bvals) {
+  const int nb = boundary_count(g);
+  const int stride = gridDim.x * blockDim.x, first = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int e = first; e < src.ns * S; e += stride) {
+    const int j = e / S, k = e - j * S;
+    ttab[j * FD_CHUNK + k] = time_factor(src, j, t0 + (double)(s0 + k) * dt);
+  }
+  for (int e = first; e < S * nb; e += stride) {
+    const int k = e / nb, q = e - k * nb;
+    int i, j;
+    boundary_node(g, q, i, j);
+    bvals[e] = boundary_at(g, *desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta,
+                           (t0 + (double)(s0 + k) * dt) + dt);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_coefficients(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
@@ -492,6 +581,28 @@ hipError_t launch_initial(const Geo& g, const pd_coeff_desc* dev_desc, double* U
 hipError_t launch_clock_init(Clock* clk, double t0, double dt, double* b0, double* b1,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_clock_init, dim3(1), dim3(64), 0, s, clk, t0, dt, b0, b1);
+  return hipGetLastError();
+}
+
+hipError_t launch_fd_weights(const Geo& lat, const pd_coeff_desc* dev_desc, const SrcInfo& src,
+                             int n_src, double dt, double* W, double* partial, int nblocks,
+                             double* lim, hipStream_t s) {
+  const long long plane = (long long)lat.n_xi * lat.n_eta;
+  hipLaunchKernelGGL(k_fd_weights, dim3(nblocks), dim3(256), 0, s, lat, dev_desc, src, n_src,
+                     dt, W, plane, partial);
+  hipLaunchKernelGGL(k_fd_limit_final, dim3(1), dim3(64), 0, s, partial, nblocks, lim);
+  return hipGetLastError();
+}
+
+hipError_t launch_fd_tables(const Geo& lat, const SrcInfo& src, const pd_coeff_desc* dev_desc,
+                            double t0, double dt, long long s0, int S, double* ttab,
+                            double* bvals, hipStream_t s) {
+  const long long work = (long long)S * (boundary_count(lat) > src.ns ? boundary_count(lat)
+                                                                       : src.ns);
+  long long blocks = (work + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(k_fd_tables, dim3((unsigned)blocks), dim3(256), 0, s, lat, src, dev_desc,
+                     t0, dt, s0, S, ttab, bvals);
   return hipGetLastError();
 }
 

@@ -968,3 +968,4 @@ pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
 
 #include "pd_batch_host.inc"
 #include "pd_closure_host.inc"
+#include "pd_fd_host.inc"

@@ -140,6 +140,32 @@ hipError_t launch_replay(const Geo& g, const SrcInfo& src, const pd_coeff_desc* 
                          double* bvals, hipStream_t s);
 hipError_t launch_initial(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
                           hipStream_t s);
+// ---------------------------------------------------------------- full-domain lattice
+// The explicit comparator on one lattice over the whole box: a Geo whose n_xi x n_eta
+// nodes are the lattice (spacings Dxi, Deta), weight planes [cC, cS, cN, cW, cE, K,
+// sd_0, sd_1] (see k_fd_weights), time-factor and Dirichlet tables per chunk of steps.
+constexpr int FD_CHUNK = 256;  // steps per table chunk
+constexpr int FD_NB = 1024;    // blocks of the weight pass (and its bound reduction)
+struct FdArgs {
+  int n_x, n_y, periodic;
+  int ns;             // time-dependent source terms (0..2)
+  int has_k;          // constant source terms present (K plane non-zero)
+  int nb;             // Dirichlet nodes
+  long long plane;    // n_x * n_y
+  const double* W;    // weight planes
+  const double* ttab; // [ns][FD_CHUNK]
+  const double* bvals;// [FD_CHUNK][nb]
+  int* flag;          // set to 1 on a non-finite value
+};
+hipError_t launch_fd_weights(const Geo& lat, const pd_coeff_desc* dev_desc, const SrcInfo& src,
+                             int n_src, double dt, double* W, double* partial, int nblocks,
+                             double* lim, hipStream_t s);
+hipError_t launch_fd_tables(const Geo& lat, const SrcInfo& src, const pd_coeff_desc* dev_desc,
+                            double t0, double dt, long long s0, int S, double* ttab,
+                            double* bvals, hipStream_t s);
+// One lattice step: V = step(U) with the tables' entry k.
+hipError_t launch_fd_step(const FdArgs& a, const double* U, double* V, int k, hipStream_t s);
+
 hipError_t launch_clock_init(Clock* clk, double t0, double dt, double* b0, double* b1,
                              hipStream_t s);
 hipError_t launch_lift_bc(const Geo& g, const int* pmap, const double* tab, const double* U,

@@ -97,6 +97,12 @@ class BatchInfo(C.Structure):
                 ("updates_per_step", C.c_int64)]
 
 
+class FdInfo(C.Structure):
+    _fields_ = [("n_x", C.c_int32), ("n_y", C.c_int32), ("workspace_bytes", C.c_size_t),
+                ("dt_limit", C.c_double), ("dt", C.c_double), ("spacing_x", C.c_double),
+                ("spacing_y", C.c_double)]
+
+
 EXPORTS = {
     "pd_create_grid": (C.c_int32, [C.POINTER(GridDesc), C.POINTER(C.c_void_p)]),
     "pd_destroy_grid": (C.c_int32, [C.c_void_p]),
@@ -167,6 +173,14 @@ EXPORTS = {
     "pd_batch_closure_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p]),
     "pd_batch_closure_stats": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64),
                                            C.POINTER(C.c_int64), C.c_int32]),
+    "pd_fd_create": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]),
+    "pd_fd_destroy": (C.c_int32, [C.c_void_p]),
+    "pd_fd_query": (C.c_int32, [C.c_void_p, C.POINTER(FdInfo)]),
+    "pd_fd_bind_workspace": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "pd_fd_prepare": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
+    "pd_fd_initial": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "pd_fd_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
+    "pd_fd_sync": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "pd_last_error": (C.c_char_p, []),
 }
 
@@ -499,6 +513,58 @@ class Batch:
 BATCH_MENU = [(2, 1, 3), (2, 1, 5), (2, 1, 6), (2, 1, 7), (2, 2, 3), (1, 1, 5), (1, 2, 3),
               (1, 3, 2), (1, 4, 2), (3, 2, 4), (3, 3, 2),
               (3, 2, 3)]  # (exchange, columns, rows) of the batch kernel's menu, by index
+
+
+class FullDomain:
+    """The full-domain lattice of a grid's problem (pd_fd_*): forward Euler with the
+    bursts' differences on one n_x x n_y lattice over the whole box."""
+
+    def __init__(self, grid, n_x, n_y, dt=None, frac=0.5):
+        self.L = lib()
+        self.grid = grid  # kept alive: the lattice uses its problem
+        self.h = C.c_void_p()
+        _check(self.L.pd_fd_create(grid.h, int(n_x), int(n_y), C.byref(self.h)))
+        need = self.query().workspace_bytes
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=grid.device)
+        base = self.ws.data_ptr()
+        _check(self.L.pd_fd_bind_workspace(self.h, C.c_void_p(base + (-base) % 256), need))
+        self.n_x, self.n_y = int(n_x), int(n_y)
+        if dt is None:
+            self.prepare(1e-300)  # any positive step: the call reports the bound
+            dt = frac * self.query().dt_limit
+        self.prepare(dt)
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            self.L.pd_fd_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def query(self):
+        info = FdInfo()
+        _check(self.L.pd_fd_query(self.h, C.byref(info)))
+        return info
+
+    def prepare(self, dt, stream=None):
+        _check(self.L.pd_fd_prepare(self.h, float(dt), _stream(stream)))
+
+    @property
+    def dt(self):
+        return self.query().dt
+
+    def new_U(self):
+        return torch.empty((self.n_y, self.n_x), dtype=torch.float64, device=self.grid.device)
+
+    def initial(self, t=0.0, U=None, stream=None):
+        U = self.new_U() if U is None else U
+        _check(self.L.pd_fd_initial(self.h, _ptr(U), float(t), _stream(stream)))
+        return U
+
+    def solve(self, U, t0, n_steps, stream=None):
+        _check(self.L.pd_fd_solve(self.h, _ptr(U), float(t0), int(n_steps), _stream(stream)))
+        return U
+
+    def sync(self, stream=None):
+        _check(self.L.pd_fd_sync(self.h, _stream(stream)))
 
 
 N_FEAT, N_PARAMS = 33, 20993

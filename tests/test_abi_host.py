@@ -147,3 +147,30 @@ def test_batch_create_rejects_members_without_coefficients(pd):
     st = pd.lib().pd_batch_create(arr, 1, C.byref(h))
     assert st == -2  # PD_ESTATE: no workspace / coefficients
     assert pd.lib().pd_batch_create(arr, 0, C.byref(h)) == -1
+
+
+def test_full_domain_lattice_host_checks(pd):
+    """pd_fd_create validates the lattice on the host; the workspace covers eight weight
+    planes and a second field buffer; calls before a workspace report a state error."""
+    g = _grid(pd, W.config1())
+    L = pd.lib()
+    h = C.c_void_p()
+    assert L.pd_fd_create(g.h, 2, 9, C.byref(h)) == -1
+    assert L.pd_fd_create(None, 9, 9, C.byref(h)) == -1
+    assert L.pd_fd_create(g.h, 33, 17, C.byref(h)) == 0
+    info = pd.FdInfo()
+    assert L.pd_fd_query(h, C.byref(info)) == 0
+    assert (info.n_x, info.n_y) == (33, 17)
+    assert info.workspace_bytes >= 9 * 33 * 17 * 8
+    assert math.isclose(info.spacing_x, 1.0 / 32) and math.isclose(info.spacing_y, 1.0 / 16)
+    assert info.dt_limit == 0.0 and info.dt == 0.0
+    assert L.pd_fd_prepare(h, 1e-6, None) == -2
+    assert L.pd_fd_solve(h, None, 0.0, 1, None) == -2
+    assert L.pd_fd_bind_workspace(h, C.c_void_p(256), 16) == -6
+    assert L.pd_fd_destroy(h) == 0
+    # a periodic xi axis divides the box into n_x intervals
+    ga = _grid(pd, W.config3(n_r=11, n_theta=16, m=9))
+    assert L.pd_fd_create(ga.h, 64, 11, C.byref(h)) == 0
+    assert L.pd_fd_query(h, C.byref(info)) == 0
+    assert math.isclose(info.spacing_x, 2 * math.pi / 64)
+    assert L.pd_fd_destroy(h) == 0

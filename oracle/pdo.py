@@ -308,6 +308,41 @@ class Oracle:
             raise FloatingPointError("oracle step status %d" % rc)
         return V
 
+    def step_refresh(self, U, t_n, n_refresh, Dt=None, dt=None, n_t=None):
+        """One macro step with the edge data refreshed during the burst.  The paper fixes
+        the edge gradients for the whole burst (Sec. 3.3 step (ii)) and names refreshing
+        them as the refinement; the reading taken here: the n_t nano steps run as
+        n_refresh sub-bursts (sub-burst q: nano steps n_t q // Q .. n_t (q + 1) // Q - 1,
+        from t_n + (n_t q // Q) dt); before each later sub-burst every patch is restricted
+        (eq. Restriction), the macro field takes those averages at the patch nodes and
+        the Dirichlet data at the sub-burst's start time on the boundary nodes, and the
+        eq. (edge) gradients are taken from that field.  Then restriction and projective
+        step as in step()."""
+        t = self.prob["time"]
+        Dt = t["dt_macro"] if Dt is None else Dt
+        dt = t["dt_micro"] if dt is None else dt
+        n_t = t["n_t"] if n_t is None else n_t
+        U = np.array(U, dtype=np.float64, order="C")
+        e = self.edge(U)
+        u = self.lift(U)
+        nodes = self.patch_map()[:, 6]
+        bnd = np.ones(U.size, dtype=bool)
+        bnd[nodes] = False
+        xi, eta = self.node_coords()
+        jj, ii = np.divmod(np.nonzero(bnd)[0], self.nx)
+        for q in range(n_refresh):
+            s0, s1 = n_t * q // n_refresh, n_t * (q + 1) // n_refresh
+            u, rc = self.burst(u, e, t_n + s0 * dt, dt, s1 - s0)
+            if rc != 0:
+                raise FloatingPointError("oracle burst status %d" % rc)
+            if q + 1 < n_refresh:
+                W = np.empty(U.size)
+                W[nodes] = self.restrict(u)
+                for j, i in zip(jj, ii):
+                    W[j * self.nx + i] = self.boundary_value(xi[i], eta[j], t_n + s1 * dt)
+                e = self.edge(W.reshape(U.shape))
+        return self.macro_update(U, self.restrict(u), t_n, Dt, n_t * dt)
+
     def solve(self, U=None, n_steps=None, t0=None):
         t = self.prob["time"]
         U = self.initial() if U is None else np.array(U, dtype=np.float64, order="C")

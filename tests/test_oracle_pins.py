@@ -561,3 +561,83 @@ def test_roundoff_floor_of_the_fp64_oracle(oracle_mod, name):
     m = make(oracle_mod, prob).patch_mask()
     floor = np.linalg.norm(a[m] - b[m]) / np.linalg.norm(b[m])
     assert 0.0 < floor < 1e-12, floor
+
+
+# ------------------------------------------------- edge data refreshed during the burst
+
+def test_refresh_with_one_sub_burst_is_the_plain_step(oracle_mod):
+    """n_refresh = 1 is step (ii) with the gradients frozen for the whole burst, Sec. 3.3."""
+    p = W.config2(n=9, m=7)
+    o = make(oracle_mod, p)
+    U = o.initial()
+    a = o.step(U, 0.01)
+    b = o.step_refresh(U, 0.01, 1)
+    assert a.tobytes() == b.tobytes()
+
+
+@pytest.mark.parametrize("n_t,Q,ratio", [(17, 2, 0.2), (17, 3, 0.2), (12, 5, 0.9)])
+def test_refresh_is_closed_form_macro_substeps(oracle_mod, n_t, Q, ratio):
+    """Constant alpha, gamma, nothing else: each nano step changes a patch average by dt
+    times the closed-form 9-point macro stencil of the field its edge data came from (see
+    test_macro_step_is_closed_form_nine_point_scheme).  With the edge data refreshed from
+    the patch averages between sub-bursts, the burst is therefore Q explicit macro
+    sub-steps of that stencil (lengths n_q dt, n_q = n_t (q+1) // Q - n_t q // Q, the
+    Dirichlet data 0 on the boundary), followed by the projective step."""
+    a, c = 0.7, 1.3
+    p = const_problem(a=a, c=c, n=9, m=7, ratio=ratio, n_t=n_t)
+    o = make(oracle_mod, p)
+    g = p["grid"]
+    D = 1.0 / (o.nx - 1)
+    Dt = 0.2 * o.dt_macro_limit()
+    dt = 0.3 * o.dt_micro_limit()
+    if n_t * dt > Dt:
+        dt = Dt / n_t
+    U = np.random.default_rng(12).normal(size=(o.ne, o.nx))
+    U[0, :] = U[-1, :] = U[:, 0] = U[:, -1] = 0.0
+
+    def wbar(h, m):
+        d = h / (m - 1)
+        mom = h * h / 12 + d * d / 6
+        return np.array([mom / (2 * D * D), 1 - mom / (D * D), mom / (2 * D * D)])
+
+    wx, we = wbar(g["h_eta"], o.me), wbar(g["h_xi"], o.mx)
+
+    def S(V):
+        d2x = V[:, 2:] - 2 * V[:, 1:-1] + V[:, :-2]
+        d2e = V[2:, :] - 2 * V[1:-1, :] + V[:-2, :]
+        Fx = wx[0] * d2x[:-2, :] + wx[1] * d2x[1:-1, :] + wx[2] * d2x[2:, :]
+        Fe = we[0] * d2e[:, :-2] + we[1] * d2e[:, 1:-1] + we[2] * d2e[:, 2:]
+        return a * Fx / D ** 2 + c * Fe / D ** 2
+
+    for step in range(3):
+        got = o.step_refresh(U, 0.0, Q, Dt=Dt, dt=dt, n_t=n_t)
+        Wq = U.copy()
+        for q in range(Q):
+            nq = n_t * (q + 1) // Q - n_t * q // Q
+            Wn = Wq.copy()
+            Wn[1:-1, 1:-1] = Wq[1:-1, 1:-1] + nq * dt * S(Wq)
+            Wq = Wn
+        V = U.copy()
+        V[1:-1, 1:-1] = U[1:-1, 1:-1] + Dt * (Wq[1:-1, 1:-1] - U[1:-1, 1:-1]) / (n_t * dt)
+        np.testing.assert_allclose(got, V, rtol=1e-10, atol=1e-10)
+        # and it differs from the frozen-gradient step (the refresh is not a no-op)
+        assert np.max(np.abs(got - o.step(U, 0.0, Dt=Dt, dt=dt, n_t=n_t))) > 1e-6
+        U = got
+
+
+def test_refresh_keeps_a_steady_quadratic(oracle_mod):
+    """A quadratic with alpha Q_xx + gamma Q_yy = 0 and Dirichlet data Q is a steady state
+    of the scheme (lift, edge data, bursts and restriction are exact on quadratics): the
+    refreshed step keeps it too."""
+    a, c = 0.7, 1.3
+    p = const_problem(a=a, c=c, n=9, m=7, n_t=12)
+    Qf = [("cart", 1.0, ("poly", 0.3, -0.2, c, 0.0), ("poly", 1.0, 0, 0, 0)),
+          ("cart", 1.0, ("poly", 1.0, 0, 0, 0), ("poly", 0.0, 0.4, -a, 0.0)),
+          ("cart", 0.5, ("poly", 0.0, 1.0, 0, 0), ("poly", 0.0, 1.0, 0, 0))]
+    p["bc"] = [(W.const(1.0), S) for S in Qf]
+    o = make(oracle_mod, p)
+    U = o.initial()
+    Dt = 0.2 * o.dt_macro_limit()
+    dt = 0.3 * o.dt_micro_limit()
+    V = o.step_refresh(U, 0.0, 4, Dt=Dt, dt=dt, n_t=12)
+    np.testing.assert_allclose(V, U, rtol=0, atol=1e-11)

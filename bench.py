@@ -306,6 +306,101 @@ def bench_closure(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_refresh(args):
+    """Config-2 macro steps with the edge data refreshed between sub-bursts
+    (pd_macro_step_refresh), against the frozen-edge fused step of the same problem."""
+    import torch
+
+    from paper_2405_08764_amd import pd
+    from paper_2405_08764_amd import workloads as W
+    prob = W.config2()
+    t = prob["time"]
+    Q = args.refresh
+    K = args.steps
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        g = pd.Grid(prob)
+        U = g.initial()
+        V = g.new_U()
+        for s in range(4):
+            g.macro_step_refresh(U, t["t0"] + s * t["dt_macro"], Q, out=V)
+            U, V = V, U
+        g.sync()
+        U = g.initial()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for s in range(K):
+            g.macro_step_refresh(U, t["t0"] + s * t["dt_macro"], Q, out=V)
+            U, V = V, U
+        torch.cuda.synchronize()
+        el = time.perf_counter() - s0
+        g.sync()
+        # the dominant kernel: one sub-burst (split-mode burst), timed with HIP events
+        state, edge = g.lift_bc(U)
+        n_sub = t["n_t"] // Q
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.kernel_reps)]
+        for a, b in evs:
+            a.record(stream)
+            g.micro_burst(state, edge, t["t0"], t["dt_micro"], n_sub)
+            b.record(stream)
+        torch.cuda.synchronize()
+        kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+        info = g.query()
+        # the frozen-edge fused step on the same problem (autotuned, graph replay)
+        gf = pd.Grid(prob)
+        Uf = gf.initial()
+        gf.autotune(Uf, reps=5)
+        gf.solve(Uf, n_steps=32)
+        gf.sync()
+        Uf = gf.initial()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        gf.solve(Uf, n_steps=K)
+        torch.cuda.synchronize()
+        t_fused = (time.perf_counter() - s0) / K
+        gf.sync()
+    per_step = W.updates_per_step(prob)
+    sub_updates = info.n_points * n_sub
+    achieved = 20 * sub_updates / kern_s
+    out = {
+        "metric": "patch-point updates/s (and macro steps/s) with the edge data refreshed "
+                  "during the burst",
+        "value": per_step * K / el, "unit": "patch-point updates/s",
+        "n_gpus": 1, "steps": K, "warmup": 4, "ms_per_step": el / K * 1e3,
+        "macro_steps_per_s": K / el,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded analytic coefficients, no dataset)",
+        "config": {"workload": f"refresh: config-2 problem (65x65 macro nodes, 17x17 micro "
+                               f"points per patch, n_t = {t['n_t']}) with the edge data "
+                               f"refreshed {Q - 1} times per burst ({Q} sub-bursts)",
+                   "n_refresh": Q, "updates_per_step": per_step},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["f64"] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["f64"], "traffic": None,
+                     "kernel": "k_burst (LDS exchange, split mode: one sub-burst)",
+                     "kernel_ms": kern_s * 1e3, "flops_per_update": 20},
+        "frozen_edge_fused_ms_per_step": t_fused * 1e3,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import pdo
+        threads = max(1, min(16, os.cpu_count() or 1))
+        o = pdo.Oracle(prob, threads=threads)
+        _ = o.coef
+        Uo = o.initial()
+        done, el_c = 0, 0.0
+        while done < 200 and (done == 0 or el_c < args.cpu_seconds):
+            s0 = time.perf_counter()
+            Uo = o.step_refresh(Uo, t["t0"] + done * t["dt_macro"], Q)
+            el_c += time.perf_counter() - s0
+            done += 1
+        out["cpu_baseline"] = {"value": per_step * done / el_c, "unit": "patch-point updates/s",
+                               "cores": o.L.pdo_get_threads(), "kind": "oracle",
+                               "sample": f"{done} refreshed macro step(s) of the full grid, "
+                                         f"{el_c:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def fd_cpu_baseline(prob, n, dt, steps):
     """The FP64 CPU oracle's lattice solver on the same lattice (OpenMP over rows): a few
     steps, the coefficient setup timed apart and excluded."""
@@ -433,7 +528,9 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config5",
-                             "full-domain"])
+                             "full-domain", "refresh"])
+    ap.add_argument("--refresh", type=int, default=5,
+                    help="refresh: sub-bursts per macro step (edge data refreshed between)")
     ap.add_argument("--fd-n", type=int, default=4097,
                     help="full-domain: lattice nodes per side")
     ap.add_argument("--fd-cpu-steps", type=int, default=200,
@@ -467,8 +564,8 @@ def main():
     ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"config4": 10, "config5": 20, "full-domain": 400}.get(args.workload,
-                                                                              1000)
+        args.steps = {"config4": 10, "config5": 20, "full-domain": 400,
+                      "refresh": 200}.get(args.workload, 1000)
     if args.pmc_summary:
         if args.workload == "full-domain":
             pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_fd_step",
@@ -499,6 +596,8 @@ def main():
         return bench_closure(args)
     if args.workload == "full-domain":
         return bench_full_domain(args)
+    if args.workload == "refresh":
+        return bench_refresh(args)
     prob, desc = workload(args.workload)
     t = prob["time"]
     torch.cuda.set_device(0)

@@ -181,6 +181,21 @@ pd_status pd_macro_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
  * pd_apply_boundary.  U_n and U_np1 must not alias. */
 pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
                         double dt_macro, double dt_micro, int32_t n_t, void* stream);
+/* One macro step with the edge data refreshed during the burst (the refinement the paper
+ * names after freezing the edge gradients for the whole burst, Sec. 3.3 step (ii)): the
+ * n_t nano steps run as n_refresh sub-bursts (sub-burst q takes nano steps
+ * n_t q / n_refresh .. n_t (q + 1) / n_refresh - 1, integer division, starting at
+ * t_n + (n_t q / n_refresh) dt_micro); between sub-bursts every patch is restricted
+ * (eq. Restriction), U_work takes the patch averages at the patch nodes and the Dirichlet
+ * data at the next sub-burst's start time on the boundary nodes, and the eq. (edge)
+ * gradients are recomputed from U_work.  Then (iv)-(vi) as pd_macro_step.  n_refresh = 1
+ * is the split form of pd_macro_step.  Caller buffers: patch_state [P][m_eta][m_xi], edge
+ * [P][4][M], Ubar [P], U_work [n_eta][n_xi] (distinct from U_n and U_np1).  PD_EINVAL
+ * unless 1 <= n_refresh <= n_t; PD_EUNSTABLE as pd_macro_step. */
+pd_status pd_macro_step_refresh(pd_grid g, const double* U_n, double* U_np1, double t_n,
+                                double dt_macro, double dt_micro, int32_t n_t,
+                                int32_t n_refresh, double* patch_state, double* edge,
+                                double* Ubar, double* U_work, void* stream);
 /* Dirichlet data u_b(t) on every boundary node of U (eq. CDR_Com_IC_BCs, eq. Ann_C_IC_BCs:
  * all four sides of a square, the two circles of the annulus). */
 pd_status pd_apply_boundary(pd_grid g, double* U, double t, void* stream);

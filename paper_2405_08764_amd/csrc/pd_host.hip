@@ -696,6 +696,39 @@ pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
   return PD_OK;
 }
 
+pd_status pd_macro_step_refresh(pd_grid g, const double* U_n, double* U_np1, double t_n,
+                                double dt_macro, double dt, int32_t n_t, int32_t n_refresh,
+                                double* state, double* edge, double* Ubar, double* U_work,
+                                void* stream) {
+  pd_status st = need_coeffs(g);
+  if (st) return st;
+  if (!U_n || !U_np1 || U_n == U_np1) return fail(PD_EINVAL, "U_n, U_np1 must be distinct non-null buffers");
+  if (!state || !edge || !Ubar || !U_work) return fail(PD_EINVAL, "null work buffer");
+  if (U_work == U_n || U_work == U_np1) return fail(PD_EINVAL, "U_work must be its own buffer");
+  if (n_refresh < 1 || n_refresh > n_t) return fail(PD_EINVAL, "need 1 <= n_refresh <= n_t");
+  if ((st = guard_macro(g, dt_macro, dt, n_t))) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_lift_bc(g->g, g->dpmap(), g->dtab(), U_n, state, edge, s));
+  for (int q = 0; q < n_refresh; ++q) {
+    const int s0 = (int)((long long)n_t * q / n_refresh);
+    const int s1 = (int)((long long)n_t * (q + 1) / n_refresh);
+    if ((st = pd_micro_burst(g, state, edge, t_n + s0 * dt, dt, s1 - s0, stream))) return st;
+    if (q + 1 < n_refresh) {
+      // the macro field at the sub-burst's end: patch averages at the patch nodes,
+      // Dirichlet data on the boundary nodes; then eq. (edge) gradients from it
+      HIPCHK(launch_restrict(g->g, state, Ubar, s));
+      HIPCHK(launch_scatter_patch_values(g->g, g->dpmap(), Ubar, U_work, s));
+      HIPCHK(launch_boundary(g->g, g->ddesc(), U_work, t_n + s1 * dt, s));
+      HIPCHK(launch_lift_bc(g->g, g->dpmap(), g->dtab(), U_work, nullptr, edge, s));
+    }
+  }
+  HIPCHK(launch_restrict(g->g, state, Ubar, s));
+  HIPCHK(launch_macro_update(g->g, g->dpmap(), U_n, Ubar, U_np1, dt_macro, n_t * dt, g->flag(), s));
+  HIPCHK(launch_boundary(g->g, g->ddesc(), U_np1, t_n + dt_macro, s));
+  return PD_OK;
+}
+
 pd_status pd_apply_boundary(pd_grid g, double* U, double t, void* stream) {
   pd_status st = need_coeffs(g);
   if (st) return st;

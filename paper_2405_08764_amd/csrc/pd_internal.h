@@ -171,6 +171,8 @@ hipError_t launch_clock_init(Clock* clk, double t0, double dt, double* b0, doubl
 hipError_t launch_lift_bc(const Geo& g, const int* pmap, const double* tab, const double* U,
                           double* state, double* edge, hipStream_t s);
 hipError_t launch_restrict(const Geo& g, const double* state, double* Ubar, hipStream_t s);
+hipError_t launch_scatter_patch_values(const Geo& g, const int* pmap, const double* Ubar,
+                                       double* U, hipStream_t s);
 hipError_t launch_macro_update(const Geo& g, const int* pmap, const double* U,
                                const double* Ubar, double* Unew, double dt_macro, double tau,
                                int* flag, hipStream_t s);

@@ -30,8 +30,8 @@ __device__ void load_devs(const int* pmap, const double* U, int p, double& c,
     for (int a = 0; a < 3; ++a) d[b][a] = U[pm[2 + 3 * b + a]] - c;
 }
 
-// Steps (i)-(ii): one thread per micro point writes the lifted value; threads with
-// q < 4 M also write one edge value.
+// Steps (i)-(ii): one thread per micro point writes the lifted value (unless state is
+// null: edge data only); threads with q < 4 M also write one edge value.
 __global__ void k_lift_bc(Geo g, const int* __restrict__ pmap, const double* __restrict__ tab,
                           const double* __restrict__ U, double* __restrict__ state,
                           double* __restrict__ edge) {
@@ -47,7 +47,7 @@ __global__ void k_lift_bc(Geo g, const int* __restrict__ pmap, const double* __r
   const double Uee = (d[2][1] + d[0][1]) / (g.Deta * g.Deta);
   const double Uxe = (d[2][2] - d[0][2] - d[2][0] + d[0][0]) / (4.0 * g.Dxi * g.Deta);
   const double c0d = -g.kap_xi * Uxx - g.kap_eta * Uee;
-  for (int q = threadIdx.x; q < pm; q += blockDim.x) {
+  for (int q = threadIdx.x; state != nullptr && q < pm; q += blockDim.x) {
     const int l = q / mx, k = q - l * mx;
     const double s = tab[to.s_xi + k], t = tab[to.s_eta + l];
     const double w = c0d + s * Ux + t * Ue + 0.5 * s * s * Uxx + s * t * Uxe + 0.5 * t * t * Uee;
@@ -89,7 +89,23 @@ __global__ void k_macro_update(Geo g, const int* __restrict__ pmap, const double
   if (!isfinite(v)) atomicOr(flag, 1);
 }
 
+// The macro field of a refresh inside a burst: each patch node takes its patch's current
+// restriction (boundary nodes are written separately).
+__global__ void k_scatter_patch_values(Geo g, const int* __restrict__ pmap,
+                                       const double* __restrict__ Ubar, double* __restrict__ U) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.P) return;
+  U[pmap[11 * p + 6]] = Ubar[p];
+}
+
 }  // namespace
+
+hipError_t launch_scatter_patch_values(const Geo& g, const int* pmap, const double* Ubar,
+                                       double* U, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_patch_values, dim3((g.P + 127) / 128), dim3(128), 0, s, g, pmap,
+                     Ubar, U);
+  return hipGetLastError();
+}
 
 hipError_t launch_lift_bc(const Geo& g, const int* pmap, const double* tab, const double* U,
                           double* state, double* edge, hipStream_t s) {

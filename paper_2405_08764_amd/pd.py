@@ -116,6 +116,10 @@ EXPORTS = {
     "pd_restrict": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_macro_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                   C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
+    "pd_macro_step_refresh": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                          C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]),
     "pd_patch_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                   C.c_double, C.c_int32, C.c_void_p]),
     "pd_apply_boundary": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
@@ -388,6 +392,27 @@ class Grid:
         out = self.new_U() if out is None else out
         _check(self.L.pd_macro_step(self.h, _ptr(U_n), _ptr(out), float(t_n), float(dt_macro),
                                     float(dt_micro), int(n_t), _ptr(Ubar), _stream()))
+        return out
+
+    def macro_step_refresh(self, U_n, t_n, n_refresh, dt_macro=None, dt_micro=None, n_t=None,
+                           out=None):
+        """pd_macro_step_refresh: the burst split into n_refresh sub-bursts with the edge
+        data recomputed between them (work buffers are kept on the grid object)."""
+        t = self.prob["time"]
+        dt_macro = t["dt_macro"] if dt_macro is None else dt_macro
+        dt_micro = t["dt_micro"] if dt_micro is None else dt_micro
+        n_t = t["n_t"] if n_t is None else n_t
+        out = self.new_U() if out is None else out
+        if getattr(self, "_refresh_bufs", None) is None:
+            f64 = dict(dtype=torch.float64, device=self.device)
+            self._refresh_bufs = (torch.empty((self.P, self.me, self.mx), **f64),
+                                  torch.empty((self.P, 4, self.M), **f64),
+                                  torch.empty((self.P,), **f64), self.new_U())
+        st, ed, ub, uw = self._refresh_bufs
+        _check(self.L.pd_macro_step_refresh(self.h, _ptr(U_n), _ptr(out), float(t_n),
+                                            float(dt_macro), float(dt_micro), int(n_t),
+                                            int(n_refresh), _ptr(st), _ptr(ed), _ptr(ub),
+                                            _ptr(uw), _stream()))
         return out
 
     def patch_step(self, U_n, t_n, out, dt_macro=None, dt_micro=None, n_t=None):

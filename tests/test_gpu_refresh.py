@@ -1,0 +1,89 @@
+"""Macro step with the edge data refreshed between sub-bursts (pd_macro_step_refresh)
+against the oracle's composition of the same steps; n_refresh = 1 against the split
+pd_macro_step; and the argument checks."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2405_08764_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def pd():
+    from paper_2405_08764_amd import pd as m
+    m.lib()
+    assert torch.cuda.is_available()
+    return m
+
+
+def say(*a):
+    print("[refresh]", *a, flush=True)
+
+
+CASES = {
+    "config1_Q3": (lambda: W.config1(n_t=11), 3, 4),
+    "tanh_Q2": (lambda: W.with_time(W.config2(n=13, m=9), dt_macro=2e-4, n_t=50), 2, 3),
+    "annulus_Q5": (lambda: W.with_time(W.config3(n_r=9, n_theta=16, m=9), dt_macro=4e-4,
+                                       n_t=23), 5, 3),
+    "sine_cdr_Q4": (lambda: W.paper_cdr(2, lam=0.2, n=9, m=7, n_t=8, T=1e-3, n_steps=2), 4, 2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_refresh_matches_oracle(pd, oracle_mod, name):
+    make, Q, steps = CASES[name]
+    prob = make()
+    g = pd.Grid(prob)
+    info = g.query()
+    t = prob["time"]
+    if t["dt_micro"] > 0.5 * info.dt_micro_limit or t["dt_macro"] > 0.5 * info.dt_macro_limit:
+        prob = W.fit_time(prob, info.dt_macro_limit, info.dt_micro_limit, steps)
+        g = pd.Grid(prob)
+        t = prob["time"]
+    say(name, "Q", Q, "n_t", t["n_t"], "steps", steps)
+    o = oracle_mod.Oracle(prob)
+    U = g.initial()
+    Uo = U.cpu().numpy().copy()
+    V = g.new_U()
+    for s in range(steps):
+        tn = t["t0"] + s * t["dt_macro"]
+        g.macro_step_refresh(U, tn, Q, out=V)
+        U, V = V, U
+        Uo = o.step_refresh(Uo, tn, Q)
+    g.sync()
+    got = U.cpu().numpy()
+    err = float(np.max(np.abs(got - Uo))) / max(1.0, float(np.max(np.abs(Uo))))
+    say(name, "max rel err", err)
+    assert err <= TOL, err
+
+
+def test_one_sub_burst_is_the_split_step(pd):
+    prob = W.config2(n=17, m=9)
+    g = pd.Grid(prob)
+    t = prob["time"]
+    U = g.initial()
+    state, edge = g.lift_bc(U)
+    g.micro_burst(state, edge, 0.02, t["dt_micro"], t["n_t"])
+    Ubar = g.restrict(state)
+    a = g.macro_step(U, 0.02, Ubar=Ubar)
+    b = g.macro_step_refresh(U, 0.02, 1)
+    g.sync()
+    assert torch.equal(a, b)
+
+
+def test_refresh_argument_checks(pd):
+    prob = W.config1()
+    g = pd.Grid(prob)
+    U = g.initial()
+    for Q in (0, prob["time"]["n_t"] + 1):
+        with pytest.raises(pd.PdError) as e:
+            g.macro_step_refresh(U, 0.0, Q)
+        assert e.value.status == -1
+    with pytest.raises(pd.PdError) as e:
+        g.macro_step_refresh(U, 0.0, 2, out=U)
+    assert e.value.status == -1
+

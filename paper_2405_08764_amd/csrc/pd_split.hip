@@ -61,19 +61,28 @@ __global__ void k_lift_bc(Geo g, const int* __restrict__ pmap, const double* __r
   }
 }
 
-// Step (iv): composite trapezoidal average, rows first then the row sums.
-__global__ void k_restrict(Geo g, const double* __restrict__ state, double* __restrict__ Ubar) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= g.P) return;
+// Step (iv): composite trapezoidal average, rows first then the row sums (each in index
+// order).  One wave per patch: lane l sums row l, lane 0 then sums the rows.
+constexpr int RS_WAVES = 4;
+__global__ __launch_bounds__(64 * RS_WAVES) void k_restrict(Geo g,
+                                                           const double* __restrict__ state,
+                                                           double* __restrict__ Ubar) {
+  __shared__ double rows[RS_WAVES][64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = blockIdx.x * RS_WAVES + w;
   const int mx = g.m_xi, me = g.m_eta;
-  const double* u = state + (long long)p * mx * me;
-  double tot = 0.0;
-  for (int l = 0; l < me; ++l) {
+  if (p < g.P && lane < me) {
+    const double* u = state + (long long)p * mx * me + (long long)lane * mx;
     double row = 0.0;
-    for (int k = 0; k < mx; ++k) row += ((k == 0 || k == mx - 1) ? 0.5 : 1.0) * u[l * mx + k];
-    tot += ((l == 0 || l == me - 1) ? 0.5 : 1.0) * row;
+    for (int k = 0; k < mx; ++k) row += ((k == 0 || k == mx - 1) ? 0.5 : 1.0) * u[k];
+    rows[w][lane] = row;
   }
-  Ubar[p] = tot / ((double)(mx - 1) * (double)(me - 1));
+  __syncthreads();
+  if (p < g.P && lane == 0) {
+    double tot = 0.0;
+    for (int l = 0; l < me; ++l) tot += ((l == 0 || l == me - 1) ? 0.5 : 1.0) * rows[w][l];
+    Ubar[p] = tot / ((double)(mx - 1) * (double)(me - 1));
+  }
 }
 
 // Steps (v)-(vi) at the patch nodes.
@@ -114,7 +123,8 @@ hipError_t launch_lift_bc(const Geo& g, const int* pmap, const double* tab, cons
 }
 
 hipError_t launch_restrict(const Geo& g, const double* state, double* Ubar, hipStream_t s) {
-  hipLaunchKernelGGL(k_restrict, dim3((g.P + 127) / 128), dim3(128), 0, s, g, state, Ubar);
+  hipLaunchKernelGGL(k_restrict, dim3((g.P + RS_WAVES - 1) / RS_WAVES), dim3(64 * RS_WAVES), 0,
+                     s, g, state, Ubar);
   return hipGetLastError();
 }
 

@@ -168,6 +168,18 @@ pd_status pd_lift_bc(pd_grid g, const double* U, double* patch_state, double* ed
  * patch_state is updated in place.  PD_EUNSTABLE if dt_micro exceeds the explicit bound. */
 pd_status pd_micro_burst(pd_grid g, double* patch_state, const double* edge, double t_n,
                          double dt_micro, int32_t n_t, void* stream);
+/* Step (iii) with the alternating-direction implicit micro solver of Sec. 4.1.1 (there
+ * n_t = 2): n_t Peaceman-Rachford steps of size dt_micro from t_n in every patch.  The
+ * bursts' micro operator (same differences and ghost-point edge data as pd_micro_burst)
+ * is split into its xi part (alpha, nu, phi/2) and eta part (gamma, omega, phi/2); each
+ * step solves (I - dt/2 L_xi) u* = (I + dt/2 L_eta) u + dt/2 s and
+ * (I - dt/2 L_eta) u' = (I + dt/2 L_xi) u* + dt/2 s, s the source at the step's half time,
+ * by tridiagonal sweeps along rows, then columns.  No explicit stability bound applies.
+ * patch_state is updated in place.  PD_EINVAL for dt_micro <= 0, n_t < 1, or patches of
+ * more than 2048 micro points (m_xi m_eta; the patch and the sweeps' scratch live in 64 KiB
+ * of LDS). */
+pd_status pd_micro_burst_adi(pd_grid g, double* patch_state, const double* edge, double t_n,
+                             double dt_micro, int32_t n_t, void* stream);
 /* Step (iv): eq. (Restriction) by the composite trapezoidal rule, Ubar[P]. */
 pd_status pd_restrict(pd_grid g, const double* patch_state, double* Ubar, void* stream);
 /* Steps (v)-(vi): U_np1 = U_n + dt_macro (Ubar - U_n)/tau at patch nodes, Dirichlet data

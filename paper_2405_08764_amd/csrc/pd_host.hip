@@ -643,6 +643,21 @@ pd_status pd_micro_burst(pd_grid g, double* state, const double* edge, double t_
   return PD_OK;
 }
 
+pd_status pd_micro_burst_adi(pd_grid g, double* state, const double* edge, double t_n,
+                             double dt, int32_t n_t, void* stream) {
+  pd_status st = need_ws(g);  // no explicit-burst launch shape needed
+  if (st) return st;
+  if (!g->coeffs_set) return fail(PD_ESTATE, "coefficients not set");
+  if (!state || !edge) return fail(PD_EINVAL, "null argument");
+  if (!(dt > 0.0) || n_t < 1) return fail(PD_EINVAL, "dt_micro must be > 0 and n_t >= 1");
+  if (adi_lds_bytes(g->g.m_xi, g->g.m_eta) > ADI_LDS_MAX)
+    return fail(PD_EINVAL, "the ADI burst holds patches of at most 2048 micro points");
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_burst_adi(g->g, g->src, g->coef(), (long long)g->g.P * g->g.m_xi * g->g.m_eta,
+                          state, edge, t_n, dt, n_t, g->flag(), static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
 pd_status pd_restrict(pd_grid g, const double* state, double* Ubar, void* stream) {
   pd_status st = need_ws(g);
   if (st) return st;

@@ -140,6 +140,13 @@ hipError_t launch_replay(const Geo& g, const SrcInfo& src, const pd_coeff_desc* 
                          double* bvals, hipStream_t s);
 hipError_t launch_initial(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
                           hipStream_t s);
+// ADI micro burst (split mode): one wave per patch, 4 m_xi m_eta doubles of LDS.
+size_t adi_lds_bytes(int mx, int me);
+constexpr size_t ADI_LDS_MAX = 65536;
+hipError_t launch_burst_adi(const Geo& g, const SrcInfo& src, const double* coef,
+                            long long plane, double* state, const double* edge, double t_n,
+                            double dt, int n_t, int* flag, hipStream_t s);
+
 // ---------------------------------------------------------------- full-domain lattice
 // The explicit comparator on one lattice over the whole box: a Geo whose n_xi x n_eta
 // nodes are the lattice (spacings Dxi, Deta), weight planes [cC, cS, cN, cW, cE, K,

@@ -113,6 +113,8 @@ EXPORTS = {
     "pd_lift_bc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_micro_burst": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                    C.c_int32, C.c_void_p]),
+    "pd_micro_burst_adi": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                       C.c_double, C.c_int32, C.c_void_p]),
     "pd_restrict": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_macro_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                   C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -376,6 +378,11 @@ class Grid:
     def micro_burst(self, state, edge, t_n, dt, n_t):
         _check(self.L.pd_micro_burst(self.h, _ptr(state), _ptr(edge), float(t_n), float(dt),
                                      int(n_t), _stream()))
+        return state
+
+    def micro_burst_adi(self, state, edge, t_n, dt, n_t):
+        _check(self.L.pd_micro_burst_adi(self.h, _ptr(state), _ptr(edge), float(t_n), float(dt),
+                                         int(n_t), _stream()))
         return state
 
     def restrict(self, state):

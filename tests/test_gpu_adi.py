@@ -1,0 +1,99 @@
+"""ADI micro burst (pd_micro_burst_adi) against the oracle's Peaceman-Rachford burst, and
+whole macro steps of the paper's Sec. 4.1.1 setup (ADI micro solver, n_t = 2) against the
+oracle's composition of the same steps."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adi
+from paper_2405_08764_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def pd():
+    from paper_2405_08764_amd import pd as m
+    m.lib()
+    assert torch.cuda.is_available()
+    return m
+
+
+def say(*a):
+    print("[adi]", *a, flush=True)
+
+
+CASES = {
+    "config1": (lambda: W.config1(), 40.0, 3),
+    "tanh": (lambda: W.config2(n=7, m=9), 60.0, 2),
+    "annulus": (lambda: W.config3(n_r=6, n_theta=8, m=9), 30.0, 4),
+    "sec411": (lambda: W.paper_cdr(1, lam=0.1, n=6, m=11), None, 2),
+    "ragged_13x7": (lambda: W.problem(W.grid("sine", 5, 6, 13, 7, gparam=0.2, conv="central"),
+                                      W.config1()["fields"], W.config1()["bc"],
+                                      W.config1()["src"], W.timing(1e-3, 1, 2)), 25.0, 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_adi_burst_matches_oracle(pd, oracle_mod, name):
+    make, factor, n_t = CASES[name]
+    prob = make()
+    g = pd.Grid(prob)
+    o = oracle_mod.Oracle(prob)
+    dt = prob["time"]["dt_micro"] if factor is None else factor * g.query().dt_micro_limit
+    say(name, "dt / explicit bound", dt / g.query().dt_micro_limit, "n_t", n_t)
+    U = g.initial() + 0.1 * torch.randn(g.new_U().shape, dtype=torch.float64,
+                                        generator=torch.Generator().manual_seed(3)).cuda()
+    state, edge = g.lift_bc(U)
+    u0 = state.cpu().numpy().copy()
+    e = edge.cpu().numpy()
+    g.micro_burst_adi(state, edge, 0.017, dt, n_t)
+    g.sync()
+    got = state.cpu().numpy()
+    ref = adi.adi_burst(prob["grid"], o.coef, u0, e, 0.017, dt, n_t, adi.time_factors(prob))
+    err = float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref))))
+    say(name, "max rel err", err)
+    assert err <= TOL, err
+
+
+def test_sec411_macro_steps_match_oracle(pd, oracle_mod):
+    """Sec. 4.1.1's setup (sine map lambda = 0.1, h = 1e-3, tau = 1e-6, 10 micro intervals,
+    n_t = 2 ADI steps): lift, ADI burst, restriction and projective step, four macro
+    steps, against the oracle's composition of its own steps."""
+    prob = W.paper_cdr(1, lam=0.1, n=11, m=11, n_steps=4, T=4 * 5e-4)
+    g = pd.Grid(prob)
+    o = oracle_mod.Oracle(prob)
+    t = prob["time"]
+    tf = adi.time_factors(prob)
+    U = g.initial()
+    Uo = U.cpu().numpy().copy()
+    for s in range(t["n_steps"]):
+        tn = t["t0"] + s * t["dt_macro"]
+        state, edge = g.lift_bc(U)
+        g.micro_burst_adi(state, edge, tn, t["dt_micro"], t["n_t"])
+        U = g.macro_step(U, tn, Ubar=g.restrict(state))
+        uo = adi.adi_burst(prob["grid"], o.coef, o.lift(Uo), o.edge(Uo), tn, t["dt_micro"],
+                           t["n_t"], tf)
+        Uo = o.macro_update(Uo, o.restrict(uo), tn, t["dt_macro"], t["n_t"] * t["dt_micro"])
+    g.sync()
+    got = U.cpu().numpy()
+    err = float(np.max(np.abs(got - Uo))) / max(1.0, float(np.max(np.abs(Uo))))
+    say("sec411 macro max rel err", err)
+    assert err <= TOL, err
+
+
+def test_adi_rejects_bad_arguments(pd):
+    g = pd.Grid(W.config1())
+    state, edge = g.lift_bc(g.initial())
+    for dt, n in ((0.0, 2), (1e-6, 0)):
+        with pytest.raises(pd.PdError) as e:
+            g.micro_burst_adi(state, edge, 0.0, dt, n)
+        assert e.value.status == -1
+    big = pd.Grid(W.config2(n=5, m=64))  # 4 * 64 * 64 doubles exceed 64 KiB of LDS
+    s2 = torch.zeros((big.P, 64, 64), dtype=torch.float64, device="cuda")
+    e2 = torch.zeros((big.P, 4, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(pd.PdError) as e:
+        big.micro_burst_adi(s2, e2, 0.0, 1e-7, 2)
+    assert e.value.status == -1 and "2048" in str(e.value)

@@ -401,6 +401,99 @@ def bench_refresh(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adi(args):
+    """Sec. 4.1.1's setup with the ADI micro solver (sine map lambda = 0.1, D = 1,
+    v = (10x, 10y), f = 20, h = 1e-3, tau = 1e-6, 10 micro intervals, n_t = 2) on a
+    GPU-sized macro grid: lift and edge data, ADI burst, restriction, projective step."""
+    import torch
+
+    from paper_2405_08764_amd import pd
+    from paper_2405_08764_amd import workloads as W
+    n = args.adi_n
+    prob = W.paper_cdr(1, lam=0.1, n=n, m=11)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    K = args.steps
+    with torch.cuda.stream(stream):
+        g = pd.Grid(prob)
+        info = g.query()
+        dtm = 0.4 * info.dt_macro_limit
+        t = prob["time"]
+        dt, n_t = t["dt_micro"], t["n_t"]
+
+        def step(U, tn):
+            state, edge = g.lift_bc(U)
+            g.micro_burst_adi(state, edge, tn, dt, n_t)
+            return g.macro_step(U, tn, dt_macro=dtm, dt_micro=dt, n_t=n_t,
+                                Ubar=g.restrict(state))
+
+        U = g.initial()
+        for s in range(4):
+            U = step(U, s * dtm)
+        g.sync()
+        U = g.initial()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for s in range(K):
+            U = step(U, s * dtm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - s0
+        g.sync()
+        state, edge = g.lift_bc(U)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.kernel_reps)]
+        for a, b in evs:
+            a.record(stream)
+            g.micro_burst_adi(state, edge, 0.0, dt, n_t)
+            b.record(stream)
+        torch.cuda.synchronize()
+        kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+    pts = info.n_points
+    n_src = len(prob["src"])
+    # per point and nano step: two tridiagonal rows (about 6 flops each), two explicit
+    # half-operator evaluations (about 8 each), the source (2 per term each half), the
+    # Thomas forward and backward passes (about 5 each)
+    flops_per_update = 2 * (6 + 8 + 2 * n_src + 5)
+    alg_bytes = pts * 8 * (2 + 5 + n_src) + info.n_patches * 4 * info.m_xi * 8
+    out = {
+        "metric": "patch-point updates/s of the ADI micro burst (Sec. 4.1.1 setup)",
+        "value": pts * n_t * K / el, "unit": "patch-point updates/s",
+        "n_gpus": 1, "steps": K, "warmup": 4, "ms_per_step": el / K * 1e3,
+        "macro_steps_per_s": K / el,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (the paper's analytic coefficients, no dataset)",
+        "config": {"workload": f"adi: Sec. 4.1.1 problem (sine map lambda 0.1, D = 1, "
+                               f"v = (10x, 10y), f = 20, exact e^(x+y+t)) on {n}x{n} macro "
+                               f"nodes, 11x11 micro points, h = 1e-3, tau = 1e-6, n_t = 2 "
+                               f"ADI steps, dt_macro at 0.4 of the macro bound",
+                   "patches": info.n_patches, "dt_macro": dtm,
+                   "dt_micro_over_explicit_bound": dt / info.dt_micro_limit},
+        "roofline": {"bound": "alu", "achieved": flops_per_update * pts * n_t / kern_s / 1e12,
+                     "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                     "frac": flops_per_update * pts * n_t / kern_s / PEAK["f64"],
+                     "traffic": None, "algorithmic_bytes": alg_bytes,
+                     "hbm_frac": alg_bytes / kern_s / 8e12,
+                     "kernel": "k_burst_adi (one ADI burst)", "kernel_ms": kern_s * 1e3,
+                     "flops_per_update": flops_per_update},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's ADI burst (numpy, dense line solves) on the first patches of the grid
+        from oracle import adi, pdo
+        o = pdo.Oracle(prob)
+        Uo = o.initial()
+        npat = 64
+        u0, e = o.lift(Uo)[:npat], o.edge(Uo)[:npat]
+        s0 = time.perf_counter()
+        adi.adi_burst(prob["grid"], o.coef[:, :npat], u0, e, 0.0, dt, n_t,
+                      adi.time_factors(prob))
+        el_c = time.perf_counter() - s0
+        out["cpu_baseline"] = {"value": npat * info.m_xi * info.m_eta * n_t / el_c,
+                               "unit": "patch-point updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one ADI burst ({n_t} steps) of {npat} patches, "
+                                         f"{el_c:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def fd_cpu_baseline(prob, n, dt, steps):
     """The FP64 CPU oracle's lattice solver on the same lattice (OpenMP over rows): a few
     steps, the coefficient setup timed apart and excluded."""
@@ -528,7 +621,9 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config5",
-                             "full-domain", "refresh"])
+                             "full-domain", "refresh", "adi"])
+    ap.add_argument("--adi-n", type=int, default=129,
+                    help="adi: macro nodes per side")
     ap.add_argument("--refresh", type=int, default=5,
                     help="refresh: sub-bursts per macro step (edge data refreshed between)")
     ap.add_argument("--fd-n", type=int, default=4097,
@@ -565,7 +660,7 @@ def main():
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"config4": 10, "config5": 20, "full-domain": 400,
-                      "refresh": 200}.get(args.workload, 1000)
+                      "refresh": 200, "adi": 200}.get(args.workload, 1000)
     if args.pmc_summary:
         if args.workload == "full-domain":
             pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_fd_step",
@@ -598,6 +693,8 @@ def main():
         return bench_full_domain(args)
     if args.workload == "refresh":
         return bench_refresh(args)
+    if args.workload == "adi":
+        return bench_adi(args)
     prob, desc = workload(args.workload)
     t = prob["time"]
     torch.cuda.set_device(0)

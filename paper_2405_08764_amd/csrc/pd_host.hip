@@ -650,8 +650,12 @@ pd_status pd_micro_burst_adi(pd_grid g, double* state, const double* edge, doubl
   if (!g->coeffs_set) return fail(PD_ESTATE, "coefficients not set");
   if (!state || !edge) return fail(PD_EINVAL, "null argument");
   if (!(dt > 0.0) || n_t < 1) return fail(PD_EINVAL, "dt_micro must be > 0 and n_t >= 1");
-  if (adi_lds_bytes(g->g.m_xi, g->g.m_eta) > ADI_LDS_MAX)
-    return fail(PD_EINVAL, "the ADI burst holds patches of at most 2048 micro points");
+  {
+    int ppb = 0, stage = 0;
+    size_t lds = 0;
+    adi_shape(g->g.m_xi, g->g.m_eta, g->src.nconst + g->src.ns, ppb, stage, lds);
+    if (ppb < 1) return fail(PD_EINVAL, "the ADI burst holds patches of at most 2048 micro points");
+  }
   HIPCHK(hipSetDevice(g->d.device));
   HIPCHK(launch_burst_adi(g->g, g->src, g->coef(), (long long)g->g.P * g->g.m_xi * g->g.m_eta,
                           state, edge, t_n, dt, n_t, g->flag(), static_cast<hipStream_t>(stream)));

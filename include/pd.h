@@ -175,9 +175,9 @@ pd_status pd_micro_burst(pd_grid g, double* patch_state, const double* edge, dou
  * step solves (I - dt/2 L_xi) u* = (I + dt/2 L_eta) u + dt/2 s and
  * (I - dt/2 L_eta) u' = (I + dt/2 L_xi) u* + dt/2 s, s the source at the step's half time,
  * by tridiagonal sweeps along rows, then columns.  No explicit stability bound applies.
- * patch_state is updated in place.  PD_EINVAL for dt_micro <= 0, n_t < 1, or patches of
- * more than 2048 micro points (m_xi m_eta; the patch and the sweeps' scratch live in 64 KiB
- * of LDS). */
+ * patch_state is updated in place.  PD_EINVAL for dt_micro <= 0, n_t < 1, or patches with
+ * 6 m_xi m_eta + 4 max(m_xi, m_eta) > 8192 (a patch, its sweeps' rows and its edge data
+ * live in 64 KiB of LDS; m up to 36 for square patches). */
 pd_status pd_micro_burst_adi(pd_grid g, double* patch_state, const double* edge, double t_n,
                              double dt_micro, int32_t n_t, void* stream);
 /* Step (iv): eq. (Restriction) by the composite trapezoidal rule, Ubar[P]. */

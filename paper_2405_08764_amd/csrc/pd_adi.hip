@@ -6,9 +6,11 @@
 // the half step:
 //   (I - dt/2 L_xi)  u*      = (I + dt/2 L_eta) u^n + dt/2 s(t + dt/2)
 //   (I - dt/2 L_eta) u^{n+1} = (I + dt/2 L_xi)  u*  + dt/2 s(t + dt/2).
-// One wave per patch, the patch in LDS; lane l solves row l of the first half step and
-// lane k column k of the second by the Thomas algorithm (the ghost-point rows stay
-// tridiagonal: the ghost folds onto the neighbour inside the patch).
+// One wave holds several patches in LDS.  Each half step first assembles the tridiagonal
+// rows and right-hand sides of every point (all lanes), then lane l eliminates row l (first
+// half) or lane k column k (second half) by the Thomas algorithm, the carried factors in
+// registers (the ghost-point rows stay tridiagonal: the ghost folds onto the neighbour
+// inside the patch).
 #include "pd_internal.h"
 
 namespace pdk {
@@ -24,7 +26,6 @@ struct AdiArgs {
   double t_n, dt;
   int n_t;
   int ppb;    // patches per wave
-  int stage;  // coefficients and source planes staged in LDS
   int* flag;
 };
 
@@ -42,190 +43,154 @@ __device__ inline void dir_weights(double a, double b, double d, bool central, d
   }
 }
 
+// Row i of (I - h L) along one line for the point at `at`: lo x_{i-1} + di x_i +
+// up x_{i+1} = rhs, with the ghost point folded at the line's ends (first, last).
+__device__ inline void line_row(double am, double ap, double ph, double h, double r,
+                                bool first, bool last, double gfirst, double glast, double d,
+                                double& lo, double& di, double& up, double& rhs) {
+  lo = -h * am;
+  up = -h * ap;
+  di = 1.0 + h * (am + ap - 0.5 * ph);
+  double cst = 0.0;
+  if (first) {  // x_{-1} = x_1 - 2 d g-
+    up += lo;
+    cst = -2.0 * d * gfirst * am;
+    lo = 0.0;
+  }
+  if (last) {  // x_m = x_{m-2} + 2 d g+
+    lo += up;
+    cst += 2.0 * d * glast * ap;
+    up = 0.0;
+  }
+  rhs = r + h * cst;
+}
+
+// Thomas elimination of one line of n entries with stride `sd` in the row arrays (lo, di,
+// up, rh; up and rh are overwritten by the eliminated factors), solution into x.
+__device__ inline void thomas_line(const double* lo, const double* di, double* up, double* rh,
+                                   double* x, int n, int sd) {
+  double c = up[0] / di[0], dd = rh[0] / di[0];
+  up[0] = c;
+  rh[0] = dd;
+  for (int i = 1; i < n; ++i) {
+    const int at = i * sd;
+    const double l_ = lo[at], den = di[at] - l_ * c;
+    c = up[at] / den;
+    dd = (rh[at] - l_ * dd) / den;
+    up[at] = c;
+    rh[at] = dd;
+  }
+  double v = dd;
+  x[(n - 1) * sd] = v;
+  for (int i = n - 2; i >= 0; --i) {
+    v = rh[i * sd] - up[i * sd] * v;
+    x[i * sd] = v;
+  }
+}
+
 __global__ __launch_bounds__(64) void k_burst_adi(AdiArgs A) {
   extern __shared__ __align__(16) double lds[];
   const int mx = A.g.m_xi, me = A.g.m_eta, M = A.g.M;
   const int pm = mx * me, line = mx > me ? mx : me;
-  // patch slot and line of this lane (A.ppb patches per wave, `line` lanes each)
+  const int per = 6 * pm + 4 * M;  // u, u*, lo, di, up, rhs, edge data
   const int slot = threadIdx.x / line, lane = threadIdx.x - slot * line;
-  const long long p = (long long)blockIdx.x * A.ppb + slot;
-  const bool live = slot < A.ppb && p < A.g.P;
-  const int nsp = A.src.nconst + A.src.ns;  // source planes
-  const int per = (4 + (A.stage ? 5 + nsp : 0)) * pm + 4 * M;
-  double* u = lds + (long long)(slot < A.ppb ? slot : 0) * per;  // [me][mx] u^n, u^{n+1}
-  double* us = u + pm;                                            // u*
-  double* cp = us + pm;                                           // Thomas scratch
-  double* dp = cp + pm;
-  double* eg = dp + pm;     // edge data [4][M]
-  double* cs = eg + 4 * M;  // staged alpha, gamma, nu, omega, phi, source planes
+  const long long p0 = (long long)blockIdx.x * A.ppb;
+  const bool live = slot < A.ppb && p0 + slot < A.g.P;
   const double dx = A.g.dxi, de = A.g.deta;
   const bool central = A.g.conv == PD_CONV_CENTRAL;
   const double h = 0.5 * A.dt;
   const long long P = A.plane;
-  const long long pp = live ? p : 0;
-  const double* Cg = A.coef + pp * pm;
-  const double* gxm = eg;
-  const double* gxp = eg + M;
-  const double* gem = eg + 2 * M;
-  const double* gep = eg + 3 * M;
-  double* st = A.state + pp * pm;
-  if (live) {
-    for (int q = lane; q < pm; q += line) u[q] = st[q];
-    for (int q = lane; q < 4 * M; q += line) eg[q] = A.edge[pp * 4 * M + q];
-    if (A.stage) {
-      for (int f = 0; f < 5; ++f)
-        for (int q = lane; q < pm; q += line) cs[f * pm + q] = Cg[f * P + q];
-      for (int c = 0; c < A.src.nconst; ++c)
-        for (int q = lane; q < pm; q += line) cs[(5 + c) * pm + q] = Cg[A.src.plane_c[c] * P + q];
-      for (int j = 0; j < A.src.ns; ++j)
-        for (int q = lane; q < pm; q += line)
-          cs[(5 + A.src.nconst + j) * pm + q] = Cg[A.src.plane_t[j] * P + q];
-    }
+  const int npts = A.ppb * pm;
+  // the patches' fields and edge data into LDS
+  for (int q = threadIdx.x; q < npts; q += 64) {
+    const int sl = q / pm, at = q - sl * pm;
+    if (p0 + sl < A.g.P) lds[sl * per + at] = A.state[(p0 + sl) * pm + at];
+  }
+  for (int q = threadIdx.x; q < A.ppb * 4 * M; q += 64) {
+    const int sl = q / (4 * M), e = q - sl * 4 * M;
+    if (p0 + sl < A.g.P) lds[sl * per + 6 * pm + e] = A.edge[(p0 + sl) * 4 * M + e];
   }
   __syncthreads();
-  // coefficient f at point `at`: from LDS when staged, else from the planes
-  auto cf = [&](int f, int at) { return A.stage ? cs[f * pm + at] : Cg[f * P + at]; };
   bool bad = false;
   for (int s = 0; s < A.n_t; ++s) {
     const double th = A.t_n + s * A.dt + 0.5 * A.dt;
     double T[2] = {0.0, 0.0};
     for (int j = 0; j < A.src.ns; ++j) T[j] = time_factor(A.src, j, th);
-    auto source = [&](int at) {
-      double v = 0.0;
-      if (A.stage) {
-        for (int c = 0; c < A.src.nconst; ++c) v += A.src.ca[c] * cs[(5 + c) * pm + at];
-        for (int j = 0; j < A.src.ns; ++j) v += T[j] * cs[(5 + A.src.nconst + j) * pm + at];
-      } else {
-        for (int c = 0; c < A.src.nconst; ++c) v += A.src.ca[c] * Cg[A.src.plane_c[c] * P + at];
-        for (int j = 0; j < A.src.ns; ++j) v += T[j] * Cg[A.src.plane_t[j] * P + at];
-      }
-      return v;
-    };
-    // first half step: lane l, row l, implicit in xi
-    if (live && lane < me) {
-      const int l = lane;
-      double* c_ = cp + lane * mx;
-      double* d_ = dp + lane * mx;
-      for (int k = 0; k < mx; ++k) {
-        const int at = l * mx + k;
-        const double ga = cf(1, at), om = cf(3, at), ph = cf(4, at);
-        double wm, wp;
-        dir_weights(ga, om, de, central, wm, wp);
-        const double uc = u[at];
-        const double uS = l > 0 ? u[at - mx] : u[at + mx] - 2.0 * de * gem[k];
-        const double uN = l < me - 1 ? u[at + mx] : u[at - mx] + 2.0 * de * gep[k];
-        const double Le = wm * uS + wp * uN - (wm + wp - 0.5 * ph) * uc;
-        const double r = uc + h * Le + h * source(at);
-        const double al = cf(0, at), nu = cf(2, at);
-        double am, ap;
+    for (int half = 0; half < 2; ++half) {
+      // assembly: every point of every patch of the block (all lanes busy)
+      for (int q = threadIdx.x; q < npts; q += 64) {
+        const int sl = q / pm, at = q - sl * pm;
+        if (p0 + sl >= A.g.P) continue;
+        double* b = lds + sl * per;
+        const double* src = half == 0 ? b : b + pm;  // u^n, then u*
+        const double* eg = b + 6 * pm;
+        const double* Cs = A.coef + (p0 + sl) * pm;
+        const int l = at / mx, k = at - l * mx;
+        const double al = Cs[at], ga = Cs[P + at], nu = Cs[2 * P + at], om = Cs[3 * P + at],
+                     ph = Cs[4 * P + at];
+        double sv = 0.0;
+        for (int c = 0; c < A.src.nconst; ++c) sv += A.src.ca[c] * Cs[A.src.plane_c[c] * P + at];
+        for (int j = 0; j < A.src.ns; ++j) sv += T[j] * Cs[A.src.plane_t[j] * P + at];
+        double am, ap, wm, wp;
         dir_weights(al, nu, dx, central, am, ap);
-        // row k of (I - h L_xi): lo x_{k-1} + di x_k + up x_{k+1} = r + h cst
-        double lo = -h * am, up = -h * ap, cst = 0.0;
-        const double di = 1.0 + h * (am + ap - 0.5 * ph);
-        if (k == 0) {  // x_{-1} = x_1 - 2 dx g-
-          up += lo;
-          cst = -2.0 * dx * gxm[l] * am;
-          lo = 0.0;
-        }
-        if (k == mx - 1) {  // x_m = x_{m-2} + 2 dx g+
-          lo += up;
-          cst += 2.0 * dx * gxp[l] * ap;
-          up = 0.0;
-        }
-        const double rhs = r + h * cst;
-        if (k == 0) {
-          c_[0] = up / di;
-          d_[0] = rhs / di;
-        } else {
-          const double den = di - lo * c_[k - 1];
-          c_[k] = up / den;
-          d_[k] = (rhs - lo * d_[k - 1]) / den;
-        }
-      }
-      double x = d_[mx - 1];
-      us[l * mx + mx - 1] = x;
-      for (int k = mx - 2; k >= 0; --k) {
-        x = d_[k] - c_[k] * x;
-        us[l * mx + k] = x;
-      }
-    }
-    __syncthreads();
-    // second half step: lane k, column k, implicit in eta
-    if (live && lane < mx) {
-      const int k = lane;
-      double* c_ = cp + lane * me;
-      double* d_ = dp + lane * me;
-      for (int l = 0; l < me; ++l) {
-        const int at = l * mx + k;
-        const double al = cf(0, at), nu = cf(2, at), ph = cf(4, at);
-        double am, ap;
-        dir_weights(al, nu, dx, central, am, ap);
-        const double uc = us[at];
-        const double uW = k > 0 ? us[at - 1] : us[at + 1] - 2.0 * dx * gxm[l];
-        const double uE = k < mx - 1 ? us[at + 1] : us[at - 1] + 2.0 * dx * gxp[l];
-        const double Lx = am * uW + ap * uE - (am + ap - 0.5 * ph) * uc;
-        const double r = uc + h * Lx + h * source(at);
-        const double ga = cf(1, at), om = cf(3, at);
-        double wm, wp;
         dir_weights(ga, om, de, central, wm, wp);
-        double lo = -h * wm, up = -h * wp, cst = 0.0;
-        const double di = 1.0 + h * (wm + wp - 0.5 * ph);
-        if (l == 0) {
-          up += lo;
-          cst = -2.0 * de * gem[k] * wm;
-          lo = 0.0;
+        const double uc = src[at];
+        double lo, di, up, rhs;
+        if (half == 0) {  // explicit in eta, implicit in xi along row l
+          const double uS = l > 0 ? src[at - mx] : src[at + mx] - 2.0 * de * eg[2 * M + k];
+          const double uN = l < me - 1 ? src[at + mx] : src[at - mx] + 2.0 * de * eg[3 * M + k];
+          const double r = uc + h * (wm * uS + wp * uN - (wm + wp - 0.5 * ph) * uc) + h * sv;
+          line_row(am, ap, ph, h, r, k == 0, k == mx - 1, eg[l], eg[M + l], dx, lo, di, up, rhs);
+        } else {  // explicit in xi, implicit in eta along column k
+          const double uW = k > 0 ? src[at - 1] : src[at + 1] - 2.0 * dx * eg[l];
+          const double uE = k < mx - 1 ? src[at + 1] : src[at - 1] + 2.0 * dx * eg[M + l];
+          const double r = uc + h * (am * uW + ap * uE - (am + ap - 0.5 * ph) * uc) + h * sv;
+          line_row(wm, wp, ph, h, r, l == 0, l == me - 1, eg[2 * M + k], eg[3 * M + k], de,
+                   lo, di, up, rhs);
         }
-        if (l == me - 1) {
-          lo += up;
-          cst += 2.0 * de * gep[k] * wp;
-          up = 0.0;
-        }
-        const double rhs = r + h * cst;
-        if (l == 0) {
-          c_[0] = up / di;
-          d_[0] = rhs / di;
-        } else {
-          const double den = di - lo * c_[l - 1];
-          c_[l] = up / den;
-          d_[l] = (rhs - lo * d_[l - 1]) / den;
+        b[2 * pm + at] = lo;
+        b[3 * pm + at] = di;
+        b[4 * pm + at] = up;
+        b[5 * pm + at] = rhs;
+      }
+      __syncthreads();
+      // the serial part: one lane per line
+      if (live) {
+        double* b = lds + slot * per;
+        if (half == 0 && lane < me) {
+          const int o = lane * mx;
+          thomas_line(b + 2 * pm + o, b + 3 * pm + o, b + 4 * pm + o, b + 5 * pm + o,
+                      b + pm + o, mx, 1);
+        } else if (half == 1 && lane < mx) {
+          const int o = lane;
+          thomas_line(b + 2 * pm + o, b + 3 * pm + o, b + 4 * pm + o, b + 5 * pm + o, b + o,
+                      me, mx);
         }
       }
-      double x = d_[me - 1];
-      u[(me - 1) * mx + k] = x;
-      bad = bad || !isfinite(x);
-      for (int l = me - 2; l >= 0; --l) {
-        x = d_[l] - c_[l] * x;
-        u[l * mx + k] = x;
-        bad = bad || !isfinite(x);
-      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  if (live)
-    for (int q = lane; q < pm; q += line) st[q] = u[q];
+  for (int q = threadIdx.x; q < npts; q += 64) {
+    const int sl = q / pm, at = q - sl * pm;
+    if (p0 + sl < A.g.P) {
+      const double v = lds[sl * per + at];
+      A.state[(p0 + sl) * pm + at] = v;
+      bad = bad || !isfinite(v);
+    }
+  }
   if (bad) atomicOr(A.flag, 1);
 }
 
 }  // namespace
 
-// Patches per wave and LDS bytes per block: with the coefficients staged when a patch's
-// field, scratch and planes fit; ppb = 0 when not even one patch's field and scratch fit.
-void adi_shape(int mx, int me, int nsp, int& ppb, int& stage, size_t& lds) {
+// Patches per wave and LDS bytes per block (6 m_xi m_eta + 4 max(m_xi, m_eta) doubles per
+// patch); ppb = 0 when not even one patch fits.
+void adi_shape(int mx, int me, int& ppb, size_t& lds) {
   const int line = mx > me ? mx : me;
-  const size_t pm = (size_t)mx * me;
-  const int lanes = 64 / line;
-  for (stage = 1; stage >= 0; --stage) {
-    const size_t per = ((4 + (stage ? 5 + nsp : 0)) * pm + 4 * (size_t)line) * sizeof(double);
-    ppb = (int)(ADI_LDS_MAX / per);
-    if (ppb > lanes) ppb = lanes;
-    if (ppb >= 1) {
-      lds = ppb * per;
-      return;
-    }
-  }
-  ppb = 0;
-  stage = 0;
-  lds = 0;
+  const size_t per = (6 * (size_t)mx * me + 4 * (size_t)line) * sizeof(double);
+  ppb = (int)(ADI_LDS_MAX / per);
+  if (ppb > 64 / line) ppb = 64 / line;
+  lds = ppb > 0 ? ppb * per : 0;
 }
 
 hipError_t launch_burst_adi(const Geo& g, const SrcInfo& src, const double* coef,
@@ -243,7 +208,7 @@ hipError_t launch_burst_adi(const Geo& g, const SrcInfo& src, const double* coef
   a.n_t = n_t;
   a.flag = flag;
   size_t lds = 0;
-  adi_shape(g.m_xi, g.m_eta, src.nconst + src.ns, a.ppb, a.stage, lds);
+  adi_shape(g.m_xi, g.m_eta, a.ppb, lds);
   if (a.ppb < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_burst_adi, dim3((g.P + a.ppb - 1) / a.ppb), dim3(64), lds, s, a);
   return hipGetLastError();

@@ -651,10 +651,11 @@ pd_status pd_micro_burst_adi(pd_grid g, double* state, const double* edge, doubl
   if (!state || !edge) return fail(PD_EINVAL, "null argument");
   if (!(dt > 0.0) || n_t < 1) return fail(PD_EINVAL, "dt_micro must be > 0 and n_t >= 1");
   {
-    int ppb = 0, stage = 0;
+    int ppb = 0;
     size_t lds = 0;
-    adi_shape(g->g.m_xi, g->g.m_eta, g->src.nconst + g->src.ns, ppb, stage, lds);
-    if (ppb < 1) return fail(PD_EINVAL, "the ADI burst holds patches of at most 2048 micro points");
+    adi_shape(g->g.m_xi, g->g.m_eta, ppb, lds);
+    if (ppb < 1)
+      return fail(PD_EINVAL, "the ADI burst needs 6 m_xi m_eta + 4 max(m_xi, m_eta) <= 8192");
   }
   HIPCHK(hipSetDevice(g->d.device));
   HIPCHK(launch_burst_adi(g->g, g->src, g->coef(), (long long)g->g.P * g->g.m_xi * g->g.m_eta,

@@ -141,10 +141,10 @@ hipError_t launch_replay(const Geo& g, const SrcInfo& src, const pd_coeff_desc* 
 hipError_t launch_initial(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
                           hipStream_t s);
 // ADI micro burst (split mode): one wave holds ppb patches (max(m_xi, m_eta) lanes each),
-// 4 m_xi m_eta doubles of LDS per patch plus, when they fit, its coefficient and source
-// planes; ppb = 0 when no patch fits in ADI_LDS_MAX.
+// 6 m_xi m_eta + 4 max(m_xi, m_eta) doubles of LDS per patch; ppb = 0 when no patch fits
+// in ADI_LDS_MAX.
 constexpr size_t ADI_LDS_MAX = 65536;
-void adi_shape(int mx, int me, int nsp, int& ppb, int& stage, size_t& lds);
+void adi_shape(int mx, int me, int& ppb, size_t& lds);
 hipError_t launch_burst_adi(const Geo& g, const SrcInfo& src, const double* coef,
                             long long plane, double* state, const double* edge, double t_n,
                             double dt, int n_t, int* flag, hipStream_t s);

@@ -91,9 +91,9 @@ def test_adi_rejects_bad_arguments(pd):
         with pytest.raises(pd.PdError) as e:
             g.micro_burst_adi(state, edge, 0.0, dt, n)
         assert e.value.status == -1
-    big = pd.Grid(W.config2(n=5, m=64))  # 4 * 64 * 64 doubles exceed 64 KiB of LDS
-    s2 = torch.zeros((big.P, 64, 64), dtype=torch.float64, device="cuda")
-    e2 = torch.zeros((big.P, 4, 64), dtype=torch.float64, device="cuda")
+    big = pd.Grid(W.config2(n=5, m=37))  # 6 * 37^2 + 4 * 37 doubles exceed 64 KiB of LDS
+    s2 = torch.zeros((big.P, 37, 37), dtype=torch.float64, device="cuda")
+    e2 = torch.zeros((big.P, 4, 37), dtype=torch.float64, device="cuda")
     with pytest.raises(pd.PdError) as e:
         big.micro_burst_adi(s2, e2, 0.0, 1e-7, 2)
-    assert e.value.status == -1 and "2048" in str(e.value)
+    assert e.value.status == -1 and "8192" in str(e.value)

@@ -114,6 +114,10 @@ int pdo_check(const pdo_grid* g, const pdo_problem* pr) {
   if (!(g->h_xi < dxi(g)) || !(g->h_eta < deta(g))) return PDO_EINVAL;
   if (g->conv != PDO_CONV_UPWIND && g->conv != PDO_CONV_CENTRAL) return PDO_EINVAL;
   if (g->c0mode != PDO_C0_TRAPEZOID && g->c0mode != PDO_C0_PRINTED) return PDO_EINVAL;
+  if (g->core_points != 0 &&
+      (g->core_points < 2 || g->core_points > g->m_xi || g->core_points > g->m_eta ||
+       (g->m_xi - g->core_points) % 2 != 0 || (g->m_eta - g->core_points) % 2 != 0))
+    return PDO_EINVAL;
   int annulus = g->geometry == PDO_GEOM_ANNULUS;
   switch (g->geometry) {
     case PDO_GEOM_IDENTITY: break;
@@ -180,15 +184,27 @@ static void edge_weights(double r, int side, double* w) {
   }
 }
 
+/* The restriction's core: the central n of the m micro points of a side (n = m, the whole
+ * patch, unless core_points is set), first index k0.  Sec. 2 of the paper leaves the
+ * averaging region open ("core average"); a smaller core is the buffer idea of gap-tooth
+ * schemes, kept here as an option. */
+static void core_range(const pdo_grid* g, int m, int* k0, int* n) {
+  *n = g->core_points > 0 ? g->core_points : m;
+  *k0 = (m - *n) / 2;
+}
+
 /* eq. (C_0): C0 = U - kappa_xi U_xixi - kappa_eta U_etaeta.  The paper obtains C0 from
  * the averaging property of eq. (Averaging); with the composite trapezoidal rule that it
- * uses for the restriction, the discrete average of s^2/2 over m points spanning h is
- * h^2/24 + delta^2/12, so the trapezoid reading keeps R(lift) = U exactly.  The printed
- * h^2/24 is kept as PDO_C0_PRINTED. */
+ * uses for the restriction, the discrete average of s^2/2 over the n core points (spanning
+ * hc = (n - 1) delta, the whole patch h by default) is hc^2/24 + delta^2/12, so the
+ * trapezoid reading keeps R(lift) = U exactly.  The printed hc^2/24 is PDO_C0_PRINTED. */
 static double kappa(const pdo_grid* g, double h, int m) {
   double d = h / (m - 1);
-  if (g->c0mode == PDO_C0_PRINTED) return h * h / 24.0;
-  return h * h / 24.0 + d * d / 12.0;
+  int k0, n;
+  core_range(g, m, &k0, &n);
+  double hc = (n - 1) * d;
+  if (g->c0mode == PDO_C0_PRINTED) return hc * hc / 24.0;
+  return hc * hc / 24.0 + d * d / 12.0;
 }
 
 int pdo_tables_size(const pdo_grid* g) {
@@ -214,8 +230,13 @@ void pdo_tables(const pdo_grid* g, double* out) {
   edge_weights(rx, +1, o); o += 3;
   edge_weights(re, -1, o); o += 3;
   edge_weights(re, +1, o); o += 3;
-  for (int k = 0; k < mx; ++k) *o++ = (k == 0 || k == mx - 1) ? 0.5 : 1.0;
-  for (int l = 0; l < me; ++l) *o++ = (l == 0 || l == me - 1) ? 0.5 : 1.0;
+  int kx0, nx, le0, ne;
+  core_range(g, mx, &kx0, &nx);
+  core_range(g, me, &le0, &ne);
+  for (int k = 0; k < mx; ++k)
+    *o++ = (k < kx0 || k > kx0 + nx - 1) ? 0.0 : ((k == kx0 || k == kx0 + nx - 1) ? 0.5 : 1.0);
+  for (int l = 0; l < me; ++l)
+    *o++ = (l < le0 || l > le0 + ne - 1) ? 0.0 : ((l == le0 || l == le0 + ne - 1) ? 0.5 : 1.0);
   *o++ = Dx;
   *o++ = De;
   *o++ = g->h_xi / (mx - 1);
@@ -694,18 +715,21 @@ int pdo_burst(const pdo_grid* g, const pdo_problem* pr, const double* coef, doub
 
 /* ---------------------------------------- step (iv): eq. (Restriction) ----------- */
 
-/* Composite trapezoidal rule over the patch in the computational coordinates divided by
- * h_xi h_eta: weights 1/2 at the edges, the delta^2 factors cancel against
- * h = (m - 1) delta. */
+/* Composite trapezoidal rule over the patch (or its core) in the computational
+ * coordinates divided by the region's area: weights 1/2 at the region's edges, the delta^2
+ * factors cancel against (n - 1) delta. */
 static real restrict_patch(const pdo_grid* g, const real* u) {
-  int mx = g->m_xi, me = g->m_eta;
+  int mx = g->m_xi, me = g->m_eta, kx0, nx, le0, ne;
+  core_range(g, mx, &kx0, &nx);
+  core_range(g, me, &le0, &ne);
   real sum = 0.0;
-  for (int l = 0; l < me; ++l) {
+  for (int l = le0; l < le0 + ne; ++l) {
     real row = 0.0;
-    for (int k = 0; k < mx; ++k) row += ((k == 0 || k == mx - 1) ? 0.5 : 1.0) * u[l * mx + k];
-    sum += ((l == 0 || l == me - 1) ? 0.5 : 1.0) * row;
+    for (int k = kx0; k < kx0 + nx; ++k)
+      row += ((k == kx0 || k == kx0 + nx - 1) ? 0.5 : 1.0) * u[l * mx + k];
+    sum += ((l == le0 || l == le0 + ne - 1) ? 0.5 : 1.0) * row;
   }
-  return sum / ((real)(mx - 1) * (real)(me - 1));
+  return sum / ((real)(nx - 1) * (real)(ne - 1));
 }
 
 void pdo_restrict(const pdo_grid* g, const double* u, double* Ubar) {

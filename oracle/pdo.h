@@ -57,6 +57,8 @@ typedef struct {
   int m_xi, m_eta;          /* micro points per patch side (edges included)      */
   int conv;                 /* first-derivative micro scheme                     */
   int c0mode;               /* reading of eq. (C_0)                              */
+  int core_points;          /* restriction over the central core_points micro     */
+                            /* points per side (0: the whole patch)               */
 } pdo_grid;
 
 /* A scalar physical field F(x,y) =

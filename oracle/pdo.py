@@ -45,7 +45,8 @@ class Grid(C.Structure):
                 ("xi1", C.c_double), ("eta0", C.c_double), ("eta1", C.c_double),
                 ("n_xi", C.c_int), ("n_eta", C.c_int), ("periodic_xi", C.c_int),
                 ("h_xi", C.c_double), ("h_eta", C.c_double), ("m_xi", C.c_int),
-                ("m_eta", C.c_int), ("conv", C.c_int), ("c0mode", C.c_int)]
+                ("m_eta", C.c_int), ("conv", C.c_int), ("c0mode", C.c_int),
+                ("core_points", C.c_int)]
 
 
 class Field(C.Structure):
@@ -183,6 +184,7 @@ def make_grid(g):
     G.m_xi, G.m_eta = g["m_xi"], g["m_eta"]
     G.conv = CONV[g["conv"]]
     G.c0mode = C0[g["c0"]]
+    G.core_points = int(g.get("core", 0))
     return G
 
 

@@ -641,3 +641,68 @@ def test_refresh_keeps_a_steady_quadratic(oracle_mod):
     dt = 0.3 * o.dt_micro_limit()
     V = o.step_refresh(U, 0.0, 4, Dt=Dt, dt=dt, n_t=12)
     np.testing.assert_allclose(V, U, rtol=0, atol=1e-11)
+
+
+# ---------------------------------------------- restriction over a central core of the patch
+
+def _core_problem(oracle_mod, core, m=11, c0="trapezoid", n=7):
+    p = const_problem(n=n, m=m, c0=c0)
+    p["grid"]["core"] = core
+    return p, make(oracle_mod, p)
+
+
+@pytest.mark.parametrize("core", [3, 5, 9])
+def test_core_restriction_moments(oracle_mod, core):
+    """The trapezoid rule over the central `core` points (spanning hc = (core - 1) delta):
+    averages of 1, s, s^2 are 1, 0 and hc^2/12 + delta^2/6; points outside the core do
+    not count; core = m is the whole-patch restriction."""
+    p, o = _core_problem(oracle_mod, core)
+    t = o.tables()
+    s_xi, s_eta = t[:o.mx], t[o.mx:o.mx + o.me]
+    d = p["grid"]["h_xi"] / (o.mx - 1)
+    hc = (core - 1) * d
+    ones = np.ones((o.P, o.me, o.mx))
+    np.testing.assert_allclose(o.restrict(ones), 1.0, rtol=1e-15)
+    np.testing.assert_allclose(o.restrict(ones * s_xi[None, None, :]), 0.0, atol=1e-18)
+    np.testing.assert_allclose(o.restrict(ones * s_xi[None, None, :] ** 2),
+                               hc * hc / 12 + d * d / 6, rtol=1e-13)
+    # a field that is zero on the core and large outside has average 0
+    k0 = (o.mx - core) // 2
+    mask = np.ones((o.me, o.mx))
+    mask[k0:k0 + core, k0:k0 + core] = 0.0
+    np.testing.assert_allclose(o.restrict(ones * 1e6 * mask[None]), 0.0, atol=1e-12)
+    pw, ow = _core_problem(oracle_mod, o.mx)
+    p0, o0 = _core_problem(oracle_mod, 0)
+    u = np.random.default_rng(3).normal(size=(o.P, o.me, o.mx))
+    assert ow.restrict(u).tobytes() == o0.restrict(u).tobytes()
+
+
+@pytest.mark.parametrize("core", [3, 7])
+def test_core_restriction_of_lift(oracle_mod, core):
+    """With C0 from the core's trapezoid average (hc^2/24 + delta^2/12), R_core(lift(U)) = U
+    exactly; the whole macro step is then exact on quadratics with constant diffusion."""
+    p, o = _core_problem(oracle_mod, core, m=9, n=9)
+    U = np.random.default_rng(8).normal(size=(o.ne, o.nx))
+    R = o.restrict(o.lift(U))
+    pm = o.patch_map()
+    np.testing.assert_allclose(R, U[pm[:, 1], pm[:, 0]], rtol=1e-13, atol=1e-13)
+    a, c = 0.7, 1.3
+    xi, eta = o.node_coords()
+    q = np.random.default_rng(9).normal(size=6)
+    Q, _, _ = _quad(q)
+    Uq = Q(xi[None, :], eta[:, None])
+    Dt = 0.2 * o.dt_macro_limit()
+    dt = 0.3 * o.dt_micro_limit()
+    n_t = max(1, int(Dt / 20 / dt))
+    V = o.step(Uq, 0.0, Dt=Dt, dt=Dt / 20 / n_t, n_t=n_t)
+    inner = (slice(1, -1), slice(1, -1))
+    np.testing.assert_allclose(V[inner], (Uq + Dt * (2 * a * q[3] + 2 * c * q[5]))[inner],
+                               rtol=1e-10, atol=1e-10)
+
+
+def test_core_size_validated(oracle_mod):
+    for core in (1, 4, 13):
+        p = const_problem(n=7, m=11)
+        p["grid"]["core"] = core
+        with pytest.raises(Exception):
+            make(oracle_mod, p)

@@ -77,6 +77,10 @@ typedef struct {
   int32_t device;                 /* HIP device ordinal                                 */
   int32_t max_sources;            /* source terms the workspace holds planes for        */
                                   /* (0 = PD_MAXTERM); pd_set_coefficients checks it    */
+  int32_t core_points;            /* restriction (eq. Restriction) over the central     */
+                                  /* core_points micro points per side, C0 from their   */
+                                  /* trapezoid average; 0 = the whole patch.  Otherwise */
+                                  /* 2 <= core_points <= m_xi, m_eta, same parity       */
 } pd_grid_desc;
 
 /* Scalar field F(x, y) = c0 + cx x + cy y + sum amp cos(kx x + ky y + ph)

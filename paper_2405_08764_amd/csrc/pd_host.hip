@@ -396,6 +396,10 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
     return fail(PD_EINVAL, "patch edges must satisfy 0 < h < Delta (patches may not overlap)");
   if (D.conv != PD_CONV_UPWIND && D.conv != PD_CONV_CENTRAL) return fail(PD_EINVAL, "bad conv");
   if (D.c0mode != PD_C0_TRAPEZOID && D.c0mode != PD_C0_PRINTED) return fail(PD_EINVAL, "bad c0mode");
+  if (D.core_points != 0 &&
+      (D.core_points < 2 || D.core_points > D.m_xi || D.core_points > D.m_eta ||
+       (D.m_xi - D.core_points) % 2 != 0 || (D.m_eta - D.core_points) % 2 != 0))
+    return fail(PD_EINVAL, "core_points must be 0 or 2..m with the parity of m_xi and m_eta");
   if (D.precision != PD_F64 && D.precision != PD_F32) return fail(PD_EINVAL, "bad precision");
   const bool box01 = D.xi0 == 0.0 && D.xi1 == 1.0 && D.eta0 == 0.0 && D.eta1 == 1.0;
   switch (D.geometry) {
@@ -432,12 +436,19 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
   G.Deta = Deta;
   G.dxi = D.h_xi / (D.m_xi - 1);
   G.deta = D.h_eta / (D.m_eta - 1);
-  // eq. (C_0): C0 = U - kappa U_xixi - kappa U_etaeta; the trapezoid reading adds
-  // delta^2/12 so that the trapezoidal restriction of the lift returns U.
-  G.kap_xi = D.c0mode == PD_C0_PRINTED ? D.h_xi * D.h_xi / 24.0
-                                       : D.h_xi * D.h_xi / 24.0 + G.dxi * G.dxi / 12.0;
-  G.kap_eta = D.c0mode == PD_C0_PRINTED ? D.h_eta * D.h_eta / 24.0
-                                        : D.h_eta * D.h_eta / 24.0 + G.deta * G.deta / 12.0;
+  // the restriction's core: the central points (the whole patch by default)
+  G.nks = D.core_points > 0 ? D.core_points : D.m_xi;
+  G.nls = D.core_points > 0 ? D.core_points : D.m_eta;
+  G.ks = (D.m_xi - G.nks) / 2;
+  G.ls = (D.m_eta - G.nls) / 2;
+  // eq. (C_0): C0 = U - kappa U_xixi - kappa U_etaeta with kappa the average of s^2/2 over
+  // the core (span hc): hc^2/24, plus delta^2/12 under the trapezoid reading so that the
+  // trapezoidal restriction of the lift returns U.
+  {
+    const double hx = (G.nks - 1) * G.dxi, he = (G.nls - 1) * G.deta;
+    G.kap_xi = D.c0mode == PD_C0_PRINTED ? hx * hx / 24.0 : hx * hx / 24.0 + G.dxi * G.dxi / 12.0;
+    G.kap_eta = D.c0mode == PD_C0_PRINTED ? he * he / 24.0 : he * he / 24.0 + G.deta * G.deta / 12.0;
+  }
   G.npx = D.periodic_xi ? D.n_xi : D.n_xi - 2;
   G.i_first = D.periodic_xi ? 0 : 1;
   G.P = G.npx * (D.n_eta - 2);
@@ -473,8 +484,10 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
   const double ew[12] = {-0.5 - rx, 2.0 * rx, 0.5 - rx, -0.5 + rx, -2.0 * rx, 0.5 + rx,
                          -0.5 - re, 2.0 * re, 0.5 - re, -0.5 + re, -2.0 * re, 0.5 + re};
   for (int q = 0; q < 12; ++q) T[g->to.ew + q] = ew[q];
-  for (int k = 0; k < mx; ++k) T[g->to.c_xi + k] = (k == 0 || k == mx - 1) ? 0.5 : 1.0;
-  for (int l = 0; l < me; ++l) T[g->to.c_eta + l] = (l == 0 || l == me - 1) ? 0.5 : 1.0;
+  for (int k = 0; k < mx; ++k)
+    T[g->to.c_xi + k] = (k < G.ks || k >= G.ks + G.nks) ? 0.0 : core_w(k, G.ks, G.nks);
+  for (int l = 0; l < me; ++l)
+    T[g->to.c_eta + l] = (l < G.ls || l >= G.ls + G.nls) ? 0.0 : core_w(l, G.ls, G.nls);
   const double sc[8] = {Dxi, Deta, G.dxi, G.deta, rx, re, G.kap_xi, G.kap_eta};
   for (int q = 0; q < 8; ++q) T[g->to.scal + q] = sc[q];
 

@@ -23,7 +23,13 @@ struct Geo {
   double dxi, deta;     // micro spacings h/(m-1)
   double kap_xi, kap_eta;
   int P, npx, i_first, M;
+  int ks, nks, ls, nls;  // restriction core: first index and points, xi and eta
 };
+
+// Trapezoid weight of index i within the core [i0, i0 + n).
+__host__ __device__ inline double core_w(int i, int i0, int n) {
+  return (i == i0 || i == i0 + n - 1) ? 0.5 : 1.0;
+}
 
 // Offsets (in doubles) of the pieces of the stencil table: the same layout that
 // pd_get_tables documents.

@@ -61,8 +61,9 @@ __global__ void k_lift_bc(Geo g, const int* __restrict__ pmap, const double* __r
   }
 }
 
-// Step (iv): composite trapezoidal average, rows first then the row sums (each in index
-// order).  One wave per patch: lane l sums row l, lane 0 then sums the rows.
+// Step (iv): composite trapezoidal average over the patch's core (the whole patch by
+// default), rows first then the row sums (each in index order).  One wave per patch:
+// lane l sums row l, lane 0 then sums the rows.
 constexpr int RS_WAVES = 4;
 __global__ __launch_bounds__(64 * RS_WAVES) void k_restrict(Geo g,
                                                            const double* __restrict__ state,
@@ -71,17 +72,17 @@ __global__ __launch_bounds__(64 * RS_WAVES) void k_restrict(Geo g,
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = blockIdx.x * RS_WAVES + w;
   const int mx = g.m_xi, me = g.m_eta;
-  if (p < g.P && lane < me) {
+  if (p < g.P && lane >= g.ls && lane < g.ls + g.nls) {
     const double* u = state + (long long)p * mx * me + (long long)lane * mx;
     double row = 0.0;
-    for (int k = 0; k < mx; ++k) row += ((k == 0 || k == mx - 1) ? 0.5 : 1.0) * u[k];
+    for (int k = g.ks; k < g.ks + g.nks; ++k) row += core_w(k, g.ks, g.nks) * u[k];
     rows[w][lane] = row;
   }
   __syncthreads();
   if (p < g.P && lane == 0) {
     double tot = 0.0;
-    for (int l = 0; l < me; ++l) tot += ((l == 0 || l == me - 1) ? 0.5 : 1.0) * rows[w][l];
-    Ubar[p] = tot / ((double)(mx - 1) * (double)(me - 1));
+    for (int l = g.ls; l < g.ls + g.nls; ++l) tot += core_w(l, g.ls, g.nls) * rows[w][l];
+    Ubar[p] = tot / ((double)(g.nks - 1) * (double)(g.nls - 1));
   }
 }
 

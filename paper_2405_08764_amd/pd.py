@@ -41,7 +41,8 @@ class GridDesc(C.Structure):
                 ("n_xi", C.c_int32), ("n_eta", C.c_int32), ("periodic_xi", C.c_int32),
                 ("h_xi", C.c_double), ("h_eta", C.c_double), ("m_xi", C.c_int32),
                 ("m_eta", C.c_int32), ("conv", C.c_int32), ("c0mode", C.c_int32),
-                ("precision", C.c_int32), ("device", C.c_int32), ("max_sources", C.c_int32)]
+                ("precision", C.c_int32), ("device", C.c_int32), ("max_sources", C.c_int32),
+                ("core_points", C.c_int32)]
 
 
 class Field(C.Structure):
@@ -275,6 +276,7 @@ def grid_desc(g, precision="f64", device=0, max_sources=0):
     D.precision = PREC[precision]
     D.device = device
     D.max_sources = max_sources
+    D.core_points = int(g.get("core", 0))
     return D
 
 

@@ -54,6 +54,11 @@ CASES = {
     "config1": lambda: W.config1(),
     "config2_small": lambda: W.config2(n=17, m=17),
     "config3_small": lambda: W.config3(n_r=11, n_theta=16, m=21),
+    "config2_core9": lambda: dict(W.config2(n=17, m=17),
+                                  grid=dict(W.config2(n=17, m=17)["grid"], core=9)),
+    "config3_core7_printed_c0": lambda: dict(
+        W.config3(n_r=11, n_theta=16, m=21),
+        grid=dict(W.config3(n_r=11, n_theta=16, m=21)["grid"], core=7, c0="printed")),
     "paper_cdr": lambda: W.paper_cdr(2, lam=0.1),
     "paper_annulus": lambda: W.paper_annulus(),
     "ragged": lambda: W.problem(W.grid("identity", 9, 6, 7, 5, box=(0, 2.0, -1.0, 0.5)),
@@ -174,3 +179,12 @@ def test_full_domain_lattice_host_checks(pd):
     assert L.pd_fd_query(h, C.byref(info)) == 0
     assert math.isclose(info.spacing_x, 2 * math.pi / 64)
     assert L.pd_fd_destroy(h) == 0
+
+
+@pytest.mark.parametrize("core", [1, 4, 19])
+def test_core_points_validated(pd, core):
+    """core_points must be 0 or 2..m with the parity of m (m = 17 here)."""
+    prob = W.config2(n=9, m=17)
+    d = pd.grid_desc(dict(prob["grid"], core=core))
+    h = C.c_void_p()
+    assert pd.lib().pd_create_grid(C.byref(d), C.byref(h)) == -1

@@ -494,6 +494,105 @@ def bench_adi(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_upwind(args):
+    """The config-2 problem with the 3- or 4-point upwind micro differences (the variant of
+    Sec. 4.1.2) through the split path: lift and edge data, higher-order upwind burst,
+    restriction, projective step.  Also times the burst kernel with each difference form,
+    the cost comparison the paper reports."""
+    import torch
+
+    from paper_2405_08764_amd import pd
+    from paper_2405_08764_amd import workloads as W
+    points, r = args.upwind_points, args.upwind_r
+    prob, desc = workload("config2")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    K = args.steps
+    t = prob["time"]
+    dtm, dt, n_t = t["dt_macro"], t["dt_micro"], t["n_t"]
+    with torch.cuda.stream(stream):
+        g = pd.Grid(prob)
+        info = g.query()
+
+        def step(U, tn):
+            state, edge = g.lift_bc(U)
+            g.micro_burst_upwind(state, edge, tn, dt, n_t, points, r)
+            return g.macro_step(U, tn, dt_macro=dtm, dt_micro=dt, n_t=n_t,
+                                Ubar=g.restrict(state))
+
+        U = g.initial()
+        for s in range(4):
+            U = step(U, s * dtm)
+        g.sync()
+        U = g.initial()
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for s in range(K):
+            U = step(U, s * dtm)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - s0
+        g.sync()
+        state, edge = g.lift_bc(U)
+        kern = {}
+        name = lambda p_, r_: f"{p_}-point" + (f" r={r_:g}" if p_ == 4 else "")
+        for pts_, r_ in ((points, r), (2, 0.0), (3, 0.0), (4, 0.5)):
+            if name(pts_, r_) in kern:
+                continue
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.kernel_reps)]
+            for a, b in evs:
+                a.record(stream)
+                g.micro_burst_upwind(state, edge, 0.0, dt, n_t, pts_, r_)
+                b.record(stream)
+            torch.cuda.synchronize()
+            kern[name(pts_, r_)] = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+        kern_s = kern[name(points, r)]
+        g.sync()
+    pts = info.n_points
+    n_src = len(prob["src"])
+    # per point and nano step: the folded 9-point cross on the increment (a multiply, eight
+    # FMAs), the source (two FMAs over the time-dependent terms) scaled by dt onto the
+    # lifted part (an FMA), the two adds forming the new increment
+    flops_per_update = 1 + 2 * 8 + 2 * 2 + 2 + 1 + 1
+    alg_bytes = pts * 8 * (2 + 5 + n_src) + info.n_patches * 4 * info.m_xi * 8
+    form = f"{points}-point" + (f" (r = {r:g})" if points == 4 else "")
+    out = {
+        "metric": "patch-point updates/s of the higher-order upwind micro burst",
+        "value": pts * n_t * K / el, "unit": "patch-point updates/s",
+        "n_gpus": 1, "steps": K, "warmup": 4, "ms_per_step": el / K * 1e3,
+        "macro_steps_per_s": K / el,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random Fourier coefficients, no dataset)",
+        "config": {"workload": f"upwind: config2 ({desc}), {form} upwind micro "
+                               f"differences, split path",
+                   "patches": info.n_patches, "n_t": n_t, "dt_macro": dtm},
+        "roofline": {"bound": "alu", "achieved": flops_per_update * pts * n_t / kern_s / 1e12,
+                     "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
+                     "frac": flops_per_update * pts * n_t / kern_s / PEAK["f64"],
+                     "traffic": None, "algorithmic_bytes": alg_bytes,
+                     "hbm_frac": alg_bytes / kern_s / 8e12,
+                     "kernel": f"k_burst_hu (one {form} burst)", "kernel_ms": kern_s * 1e3,
+                     "kernel_ms_by_form": {k: v * 1e3 for k, v in kern.items()},
+                     "flops_per_update": flops_per_update},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's burst (numpy) on the first patches of the grid
+        from oracle import adi, pdo, upwind
+        o = pdo.Oracle(prob)
+        Uo = o.initial()
+        npat = 64
+        u0, e = o.lift(Uo)[:npat], o.edge(Uo)[:npat]
+        s0 = time.perf_counter()
+        upwind.burst(prob["grid"], o.coef[:, :npat], u0, e, 0.0, dt, n_t,
+                     adi.time_factors(prob), points, r)
+        el_c = time.perf_counter() - s0
+        out["cpu_baseline"] = {"value": npat * info.m_xi * info.m_eta * n_t / el_c,
+                               "unit": "patch-point updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one {form} burst ({n_t} steps) of {npat} "
+                                         f"patches, {el_c:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def fd_cpu_baseline(prob, n, dt, steps):
     """The FP64 CPU oracle's lattice solver on the same lattice (OpenMP over rows): a few
     steps, the coefficient setup timed apart and excluded."""
@@ -621,9 +720,13 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="config2",
                     choices=["config1", "config2", "config3", "config4", "config5",
-                             "full-domain", "refresh", "adi"])
+                             "full-domain", "refresh", "adi", "upwind"])
     ap.add_argument("--adi-n", type=int, default=129,
                     help="adi: macro nodes per side")
+    ap.add_argument("--upwind-points", type=int, default=3, choices=[2, 3, 4],
+                    help="upwind: the micro first difference (2-, 3- or 4-point)")
+    ap.add_argument("--upwind-r", type=float, default=0.5,
+                    help="upwind: r of the 4-point difference")
     ap.add_argument("--refresh", type=int, default=5,
                     help="refresh: sub-bursts per macro step (edge data refreshed between)")
     ap.add_argument("--fd-n", type=int, default=4097,
@@ -660,7 +763,7 @@ def main():
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"config4": 10, "config5": 20, "full-domain": 400,
-                      "refresh": 200, "adi": 200}.get(args.workload, 1000)
+                      "refresh": 200, "adi": 200, "upwind": 200}.get(args.workload, 1000)
     if args.pmc_summary:
         if args.workload == "full-domain":
             pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_fd_step",
@@ -695,6 +798,8 @@ def main():
         return bench_refresh(args)
     if args.workload == "adi":
         return bench_adi(args)
+    if args.workload == "upwind":
+        return bench_upwind(args)
     prob, desc = workload(args.workload)
     t = prob["time"]
     torch.cuda.set_device(0)

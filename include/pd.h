@@ -184,6 +184,25 @@ pd_status pd_micro_burst(pd_grid g, double* patch_state, const double* edge, dou
  * live in 64 KiB of LDS; m up to 36 for square patches). */
 pd_status pd_micro_burst_adi(pd_grid g, double* patch_state, const double* edge, double t_n,
                              double dt_micro, int32_t n_t, void* stream);
+/* Step (iii) with the higher-order upwind convection differences of Sec. 4.1.2: n_t
+ * forward-Euler nano steps of size dt_micro from t_n in every patch, the 3-point second
+ * differences and the source as in pd_micro_burst, the first differences by
+ *   points = 3: (3 u_i - 4 u_{i-1} + u_{i-2}) / (2 dp),
+ *   points = 4: (u_{i+1} - u_{i-1}) / (2 dp) + r/(3 dp) (u_{i-2} - 3 u_{i-1} + 3 u_i - u_{i+1})
+ *               (r = 1/2 is third order, r = 0 the central difference),
+ *   points = 2: (u_i - u_{i-1}) / dp (the 2-point upwind difference),
+ * each taken as printed where the velocity component is >= 0 and mirrored (i -> -i, sign
+ * flipped) where it is < 0, whatever the grid's convection option.  The edge gradients
+ * g-, g+ of edge [P][4][M] enter through two ghost layers: u_{-1} = u_1 - 2 dp g-,
+ * u_{-2} = u_2 - 4 dp g-, u_m = u_{m-2} + 2 dp g+, u_{m+1} = u_{m-3} + 4 dp g+.
+ * patch_state [P][m_eta][m_xi] FP64 is updated in place.  No stability bound is checked
+ * (the 2-point bound of pd_query is a guide for diffusion-dominated patches); a
+ * non-finite result sets the flag pd_sync reports as PD_EUNSTABLE.  PD_EINVAL for
+ * dt_micro <= 0, n_t < 1, points outside 2..4, non-finite r, or patches with m_xi or
+ * m_eta < 3 or m_xi m_eta > 1024; PD_ESTATE before coefficients are set. */
+pd_status pd_micro_burst_upwind(pd_grid g, double* patch_state, const double* edge,
+                                double t_n, double dt_micro, int32_t n_t, int32_t points,
+                                double r, void* stream);
 /* Step (iv): eq. (Restriction) by the composite trapezoidal rule, Ubar[P]. */
 pd_status pd_restrict(pd_grid g, const double* patch_state, double* Ubar, void* stream);
 /* Steps (v)-(vi): U_np1 = U_n + dt_macro (Ubar - U_n)/tau at patch nodes, Dirichlet data

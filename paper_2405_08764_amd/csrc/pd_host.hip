@@ -676,6 +676,30 @@ pd_status pd_micro_burst_adi(pd_grid g, double* state, const double* edge, doubl
   return PD_OK;
 }
 
+pd_status pd_micro_burst_upwind(pd_grid g, double* state, const double* edge, double t_n,
+                                double dt, int32_t n_t, int32_t points, double r,
+                                void* stream) {
+  pd_status st = need_ws(g);  // no explicit-burst launch shape needed
+  if (st) return st;
+  if (!g->coeffs_set) return fail(PD_ESTATE, "coefficients not set");
+  if (!state || !edge) return fail(PD_EINVAL, "null argument");
+  if (!(dt > 0.0) || n_t < 1) return fail(PD_EINVAL, "dt_micro must be > 0 and n_t >= 1");
+  if (points < 2 || points > 4) return fail(PD_EINVAL, "points must be 2, 3 or 4");
+  if (!std::isfinite(r)) return fail(PD_EINVAL, "r must be finite");
+  {
+    int ppb = 0;
+    size_t lds = 0;
+    hu_shape(g->g.m_xi, g->g.m_eta, ppb, lds);
+    if (ppb < 1)
+      return fail(PD_EINVAL, "the upwind burst needs 3 <= m_xi, m_eta and m_xi m_eta <= 1024");
+  }
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_burst_hu(g->g, g->src, g->coef(), (long long)g->g.P * g->g.m_xi * g->g.m_eta,
+                         state, edge, t_n, dt, n_t, points, r, g->flag(),
+                         static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
 pd_status pd_restrict(pd_grid g, const double* state, double* Ubar, void* stream) {
   pd_status st = need_ws(g);
   if (st) return st;

@@ -155,6 +155,15 @@ hipError_t launch_burst_adi(const Geo& g, const SrcInfo& src, const double* coef
                             long long plane, double* state, const double* edge, double t_n,
                             double dt, int n_t, int* flag, hipStream_t s);
 
+// Explicit burst with the 2-, 3- or 4-point upwind first differences (pd_upwind.hip): up to
+// 1024 micro points per block, the patches' ghost-framed tiles within HU_LDS_MAX.
+constexpr size_t HU_LDS_MAX = 65536;
+void hu_shape(int mx, int me, int& ppb, size_t& lds);
+hipError_t launch_burst_hu(const Geo& g, const SrcInfo& src, const double* coef,
+                           long long plane, double* state, const double* edge, double t_n,
+                           double dt, int n_t, int points, double r, int* flag,
+                           hipStream_t s);
+
 // ---------------------------------------------------------------- full-domain lattice
 // The explicit comparator on one lattice over the whole box: a Geo whose n_xi x n_eta
 // nodes are the lattice (spacings Dxi, Deta), weight planes [cC, cS, cN, cW, cE, K,

@@ -116,6 +116,9 @@ EXPORTS = {
                                    C.c_int32, C.c_void_p]),
     "pd_micro_burst_adi": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                        C.c_double, C.c_int32, C.c_void_p]),
+    "pd_micro_burst_upwind": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                          C.c_double, C.c_int32, C.c_int32, C.c_double,
+                                          C.c_void_p]),
     "pd_restrict": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_macro_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                   C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -385,6 +388,12 @@ class Grid:
     def micro_burst_adi(self, state, edge, t_n, dt, n_t):
         _check(self.L.pd_micro_burst_adi(self.h, _ptr(state), _ptr(edge), float(t_n), float(dt),
                                          int(n_t), _stream()))
+        return state
+
+    def micro_burst_upwind(self, state, edge, t_n, dt, n_t, points=3, r=0.5):
+        _check(self.L.pd_micro_burst_upwind(self.h, _ptr(state), _ptr(edge), float(t_n),
+                                            float(dt), int(n_t), int(points), float(r),
+                                            _stream()))
         return state
 
     def restrict(self, state):

@@ -30,6 +30,8 @@ CASES = {
     "tanh": (lambda: W.config2(n=7, m=9), 60.0, 2),
     "annulus": (lambda: W.config3(n_r=6, n_theta=8, m=9), 30.0, 4),
     "sec411": (lambda: W.paper_cdr(1, lam=0.1, n=6, m=11), None, 2),
+    "m27": (lambda: W.config2(n=5, m=27), 40.0, 2),  # large patches: one per wave
+    "m31": (lambda: W.config2(n=5, m=31), 40.0, 2),
     "ragged_13x7": (lambda: W.problem(W.grid("sine", 5, 6, 13, 7, gparam=0.2, conv="central"),
                                       W.config1()["fields"], W.config1()["bc"],
                                       W.config1()["src"], W.timing(1e-3, 1, 2)), 25.0, 3),

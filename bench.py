@@ -40,6 +40,7 @@ BURST_SOURCES = ["pd_burst.inc", "pd_internal.h", "pd_burst_x_f64.hip", "pd_burs
 
 
 FD_SOURCES = ["pd_fd.hip", "pd_internal.h"]
+HU_SOURCES = ["pd_upwind.hip", "pd_internal.h"]
 
 
 def burst_source_hash(files=None):
@@ -548,6 +549,16 @@ def bench_upwind(args):
             kern[name(pts_, r_)] = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
         kern_s = kern[name(points, r)]
         g.sync()
+        if args.calibrate_copy:
+            # the streaming kernel of known traffic the counter summary is scaled by
+            m = args.calibrate_copy * (1 << 20) // 8
+            src = torch.ones(m, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(2):
+                torch.mul(src, 1.0, out=dst)
+            torch.cuda.synchronize()
+            del src, dst
+    traffic = read_traffic("k_burst_hu", "upwind", "f64", "hu", HU_SOURCES)
     pts = info.n_points
     n_src = len(prob["src"])
     # per point and nano step: the folded 9-point cross on the increment (a multiply, eight
@@ -569,7 +580,7 @@ def bench_upwind(args):
         "roofline": {"bound": "alu", "achieved": flops_per_update * pts * n_t / kern_s / 1e12,
                      "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
                      "frac": flops_per_update * pts * n_t / kern_s / PEAK["f64"],
-                     "traffic": None, "algorithmic_bytes": alg_bytes,
+                     "traffic": traffic, "algorithmic_bytes": alg_bytes,
                      "hbm_frac": alg_bytes / kern_s / 8e12,
                      "kernel": f"k_burst_hu (one {form} burst)", "kernel_ms": kern_s * 1e3,
                      "kernel_ms_by_form": {k: v * 1e3 for k, v in kern.items()},
@@ -770,6 +781,12 @@ def main():
                         args.calibrate_copy or 256,
                         traffic_file("k_fd_step", args.workload, "f64"), args.pmc_command,
                         args.workload, "f64", "fd", FD_SOURCES)
+            return
+        if args.workload == "upwind":
+            pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_burst_hu",
+                        args.calibrate_copy or 256,
+                        traffic_file("k_burst_hu", args.workload, "f64"), args.pmc_command,
+                        args.workload, "f64", "hu", HU_SOURCES)
             return
         kernel = KERNEL_NAME[int(args.pmc_shape.split(",")[0])]
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], kernel + "<",

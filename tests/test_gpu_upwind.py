@@ -82,6 +82,14 @@ def test_long_burst_matches_oracle(pd, oracle_mod):
     assert err <= TOL, err
 
 
+def test_burst_beyond_one_time_table_chunk(pd, oracle_mod):
+    """300 nano steps with a time-dependent source: the kernel's table of source time
+    factors is refilled every 256 steps."""
+    err = burst_case(pd, oracle_mod, W.config2(n=5, m=9), 4, 0.5, 300, 0.2, 13)
+    say("300-step burst max rel err", err)
+    assert err <= TOL, err
+
+
 @pytest.mark.parametrize("conv", ["upwind", "central"])
 def test_reduces_to_the_explicit_burst(pd, conv):
     """points = 2 on an upwind grid and points = 4 with r = 0 on a central grid are the

@@ -6,6 +6,12 @@ the forward-Euler burst in every patch, restriction and the projective update, p
 Dirichlet boundary, replayed from a HIP graph.  Default workload: the stretched unit square
 (tanh stretching, 65x65 macro nodes, 17x17 micro points per patch, random Fourier-mode
 coefficients) in FP64.  Prints one JSON line.
+
+Other workloads (--workload): config1 and config3 (the same fused step on the small square
+and the annulus), config4 (the batched persistent form), config5 (the learned closure),
+full-domain (the explicit comparator on one fine lattice), refresh (edge data refreshed
+between sub-bursts), adi (the ADI micro solver on the Sec. 4.1.1 setup) and upwind (the
+3- or 4-point upwind micro differences on the config 2 problem).
 """
 import argparse
 import json

@@ -22,7 +22,8 @@ import numpy as np
 
 
 def extend(u, gm, gp, d):
-    """Rows of u [n][m] with two ghost points on each side: [n][m + 4]."""
+    """Rows of u [n][m] with two ghost points on each side: [n][m + 4] (the Neumann edge
+    data of eq. (edge) at one and two spacings past the edge)."""
     n, m = u.shape
     e = np.empty((n, m + 4))
     e[:, 2:m + 2] = u
@@ -35,7 +36,8 @@ def extend(u, gm, gp, d):
 
 def first_difference(e, nu, d, points, r):
     """Upwind first difference along the rows of an extended field e [n][m + 4] at its m
-    inner points; nu [n][m] selects the side."""
+    inner points; nu [n][m] selects the side (the 2-, 3- and 4-point formulas of
+    Sec. 4.1.2)."""
     um2, um1, u0, up1, up2 = e[:, :-4], e[:, 1:-3], e[:, 2:-2], e[:, 3:-1], e[:, 4:]
     if points == 2:
         back = (u0 - um1) / d
@@ -52,12 +54,14 @@ def first_difference(e, nu, d, points, r):
 
 
 def second_difference(e, d):
+    """3-point central second difference of the bursts' diffusion terms (Sec. 4.1.1)."""
     return (e[:, 3:-1] - 2.0 * e[:, 2:-2] + e[:, 1:-3]) / (d * d)
 
 
 def operator(u, alpha, gamma, nu, om, phi, src, edge, dx, de, points, r):
     """alpha u_xixi + gamma u_etaeta - nu u_xi - omega u_eta + phi u + src on one patch
-    u [m_eta][m_xi]; edge = (g_xi-, g_xi+, g_eta-, g_eta+), each of length >= the side."""
+    u [m_eta][m_xi] (eq. (Computational_Problem) discretised); edge = (g_xi-, g_xi+,
+    g_eta-, g_eta+), each of length >= the side."""
     me, mx = u.shape
     gxm, gxp, gem, gep = edge
     ex = extend(u, gxm[:me], gxp[:me], dx)
@@ -70,8 +74,8 @@ def operator(u, alpha, gamma, nu, om, phi, src, edge, dx, de, points, r):
 
 
 def burst(grid, coef, u, edge, t_n, dt, n_t, tfac, points, r=0.5):
-    """n_t forward-Euler nano steps of every patch (source at the old time level, as in the
-    2-point burst).  coef [5 + n_src][P][me][mx]; u [P][me][mx] (not modified); edge
+    """n_t forward-Euler nano steps of every patch, step (iii) of Sec. 3.3 (source at the
+    old time level, as in the 2-point burst).  coef [5 + n_src][P][me][mx]; u [P][me][mx] (not modified); edge
     [P][4][M]; tfac(t) -> the source terms' time factors."""
     mx, me = grid["m_xi"], grid["m_eta"]
     dx, de = grid["h_xi"] / (mx - 1), grid["h_eta"] / (me - 1)

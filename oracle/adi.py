@@ -20,13 +20,15 @@ import numpy as np
 
 
 def _parts(coef, p, mx, me):
-    """alpha, gamma, nu, omega, phi and the source planes of patch p, [me][mx] each."""
+    """alpha, gamma, nu, omega, phi and the source planes of patch p, [me][mx] each (the
+    coefficient list of eq. (Computational_Problem))."""
     c = coef[:, p]
     return c[0], c[1], c[2], c[3], c[4], c[5:]
 
 
 def op_xi(u, alpha, nu, phi, gxm, gxp, dx, central):
-    """L_xi u for a patch field u [me][mx] (affine: includes the ghost constants)."""
+    """L_xi u for a patch field u [me][mx] (affine: includes the ghost constants): the xi
+    half of the split operator, Sec. 4.1.1."""
     me, mx = u.shape
     uW = np.empty_like(u)
     uE = np.empty_like(u)
@@ -43,6 +45,7 @@ def op_xi(u, alpha, nu, phi, gxm, gxp, dx, central):
 
 
 def op_eta(u, gamma, om, phi, gem, gep, de, central):
+    """L_eta u, the eta half of the split operator (Sec. 4.1.1), by transposition."""
     return op_xi(u.T, gamma.T, om.T, phi.T, gem, gep, de, central).T
 
 
@@ -64,7 +67,8 @@ def _solve_lines(apply, rhs, h):
 
 
 def adi_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
-    """n_t Peaceman-Rachford nano steps of every patch.  grid: dict with h_xi, h_eta,
+    """n_t Peaceman-Rachford nano steps of every patch (the ADI micro solver of
+    Sec. 4.1.1).  grid: dict with h_xi, h_eta,
     m_xi, m_eta, conv; coef [5 + n_src][P][me][mx]; u [P][me][mx] (not modified);
     edge [P][4][M] (xi-, xi+, eta-, eta+); tfac(t) -> the source time factors."""
     mx, me = grid["m_xi"], grid["m_eta"]
@@ -90,8 +94,8 @@ def adi_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
 
 
 def fe_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
-    """Forward Euler with the same operator (cross-check of the operator against the C
-    oracle's explicit burst)."""
+    """Forward Euler with the same operator, step (iii) of Sec. 3.3 (cross-check of the
+    operator against the C oracle's explicit burst)."""
     mx, me = grid["m_xi"], grid["m_eta"]
     dx, de = grid["h_xi"] / (mx - 1), grid["h_eta"] / (me - 1)
     central = grid["conv"] == "central"
@@ -111,7 +115,7 @@ def fe_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
 
 def time_factors(prob):
     """T(t) of every source term of a problem description (constant a; a e^{b t};
-    a + b sin(c t))."""
+    a + b sin(c t)), the time factors of the worked sources of Sec. 4."""
     terms = [tf for (tf, _, _) in prob["src"]]
 
     def T(t):

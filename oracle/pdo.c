@@ -9,7 +9,12 @@
  *   gcc ... -DPDO_REAL="long double" pdo.c -o libpdo_ld.so -lm
  *
  * Parity pins (each checked by a CPU test against something other than this file):
- *   coefficients      Sec. 4.1.1, 4.1.2 and 4.2 closed-form coefficient lists
+ *   coefficients      Sec. 4.1.1, 4.1.2 and 4.2 closed-form coefficient lists; on every
+ *                     other map and field kind (tanh map, Fourier D11 != D22 and v, polar
+ *                     k(r, theta), Fourier fields on the annulus) the transformed operator
+ *                     of eq. (Computational_Problem) against eq. (Physical_Problem)
+ *                     differentiated symbolically, with the source planes and the map
+ *                     derivatives, and planted mistakes in these branches rejected
  *   source            the printed sources of Sec. 4.1.1 / 4.1.2 (exact solution e^{x+y+t})
  *   edge gradients    exact derivative of quadratic macro fields; eq. (edge) weights
  *   lift              quadratic exactness; restriction of the lift returns U

@@ -218,8 +218,28 @@ def _check(status):
         raise PdError(status, lib().pd_last_error().decode())
 
 
-def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+def _ptr(t, numel=0, dtype=torch.float64, device=None, name="tensor"):
+    """Device address of t for the C ABI, after the checks the ABI cannot make itself: it
+    takes raw pointers without lengths, so a host tensor, another dtype, a strided view,
+    a buffer shorter than the call's layout or a tensor on another device would become an
+    out-of-bounds device access.  Raises PdError (PD_EINVAL) before any library call.
+    The checks run type, dtype, layout, length, then placement, so each is reachable
+    with host tensors too."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise PdError(-1, f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if dtype is not None and t.dtype != dtype:
+        raise PdError(-1, f"{name}: dtype {t.dtype}, the call needs {dtype}")
+    if not t.is_contiguous():
+        raise PdError(-1, f"{name}: must be contiguous")
+    if t.numel() < numel:
+        raise PdError(-1, f"{name}: {t.numel()} elements, the call's layout needs {numel}")
+    if not t.is_cuda:
+        raise PdError(-1, f"{name}: must be a device tensor, got one on {t.device}")
+    if device is not None and t.device != device:
+        raise PdError(-1, f"{name}: on {t.device}, the handle lives on {device}")
+    return C.c_void_p(t.data_ptr())
 
 
 def _stream(stream=None):
@@ -343,6 +363,19 @@ class Grid:
         _check(self.L.pd_set_coefficients(self.h, C.byref(self._cd), _stream(stream)))
         self.info = self.query()
 
+    # -- checked device pointers of the call layouts (include/pd.h)
+    def _U(self, t, name="U"):
+        return _ptr(t, self.ne * self.nx, torch.float64, self.device, name)
+
+    def _state(self, t, name="patch_state"):
+        return _ptr(t, self.P * self.me * self.mx, torch.float64, self.device, name)
+
+    def _edge(self, t, name="edge"):
+        return _ptr(t, self.P * 4 * self.M, torch.float64, self.device, name)
+
+    def _perpatch(self, t, name="Ubar"):
+        return _ptr(t, self.P, torch.float64, self.device, name)
+
     def set_option(self, option, value):
         _check(self.L.pd_set_option(self.h, option, int(value)))
         self.info = self.query()
@@ -361,7 +394,9 @@ class Grid:
     def coefficients(self):
         nc = 5 + len(self.prob["src"])
         out = torch.empty((nc, self.P, self.me, self.mx), dtype=torch.float64, device=self.device)
-        _check(self.L.pd_copy_coefficients(self.h, _ptr(out), _stream()))
+        _check(self.L.pd_copy_coefficients(
+            self.h, _ptr(out, nc * self.P * self.me * self.mx, torch.float64, self.device,
+                         "coefficients"), _stream()))
         return out
 
     # -- the steps
@@ -371,34 +406,37 @@ class Grid:
     def initial(self, t=None, U=None):
         U = self.new_U() if U is None else U
         t = self.prob["time"]["t0"] if t is None else t
-        _check(self.L.pd_initial(self.h, _ptr(U), float(t), _stream()))
+        _check(self.L.pd_initial(self.h, self._U(U), float(t), _stream()))
         return U
 
     def lift_bc(self, U):
         state = torch.empty((self.P, self.me, self.mx), dtype=torch.float64, device=self.device)
         edge = torch.empty((self.P, 4, self.M), dtype=torch.float64, device=self.device)
-        _check(self.L.pd_lift_bc(self.h, _ptr(U), _ptr(state), _ptr(edge), _stream()))
+        _check(self.L.pd_lift_bc(self.h, self._U(U), self._state(state), self._edge(edge),
+                                 _stream()))
         return state, edge
 
     def micro_burst(self, state, edge, t_n, dt, n_t):
-        _check(self.L.pd_micro_burst(self.h, _ptr(state), _ptr(edge), float(t_n), float(dt),
+        _check(self.L.pd_micro_burst(self.h, self._state(state), self._edge(edge), float(t_n),
+                                     float(dt),
                                      int(n_t), _stream()))
         return state
 
     def micro_burst_adi(self, state, edge, t_n, dt, n_t):
-        _check(self.L.pd_micro_burst_adi(self.h, _ptr(state), _ptr(edge), float(t_n), float(dt),
+        _check(self.L.pd_micro_burst_adi(self.h, self._state(state), self._edge(edge), float(t_n),
+                                         float(dt),
                                          int(n_t), _stream()))
         return state
 
     def micro_burst_upwind(self, state, edge, t_n, dt, n_t, points=3, r=0.5):
-        _check(self.L.pd_micro_burst_upwind(self.h, _ptr(state), _ptr(edge), float(t_n),
+        _check(self.L.pd_micro_burst_upwind(self.h, self._state(state), self._edge(edge), float(t_n),
                                             float(dt), int(n_t), int(points), float(r),
                                             _stream()))
         return state
 
     def restrict(self, state):
         Ub = torch.empty(self.P, dtype=torch.float64, device=self.device)
-        _check(self.L.pd_restrict(self.h, _ptr(state), _ptr(Ub), _stream()))
+        _check(self.L.pd_restrict(self.h, self._state(state), self._perpatch(Ub), _stream()))
         return Ub
 
     def macro_step(self, U_n, t_n, dt_macro=None, dt_micro=None, n_t=None, Ubar=None,
@@ -408,8 +446,9 @@ class Grid:
         dt_micro = t["dt_micro"] if dt_micro is None else dt_micro
         n_t = t["n_t"] if n_t is None else n_t
         out = self.new_U() if out is None else out
-        _check(self.L.pd_macro_step(self.h, _ptr(U_n), _ptr(out), float(t_n), float(dt_macro),
-                                    float(dt_micro), int(n_t), _ptr(Ubar), _stream()))
+        _check(self.L.pd_macro_step(self.h, self._U(U_n, "U_n"), self._U(out, "U_np1"), float(t_n),
+                                    float(dt_macro), float(dt_micro), int(n_t),
+                                    self._perpatch(Ubar), _stream()))
         return out
 
     def macro_step_refresh(self, U_n, t_n, n_refresh, dt_macro=None, dt_micro=None, n_t=None,
@@ -427,16 +466,17 @@ class Grid:
                                   torch.empty((self.P, 4, self.M), **f64),
                                   torch.empty((self.P,), **f64), self.new_U())
         st, ed, ub, uw = self._refresh_bufs
-        _check(self.L.pd_macro_step_refresh(self.h, _ptr(U_n), _ptr(out), float(t_n),
-                                            float(dt_macro), float(dt_micro), int(n_t),
-                                            int(n_refresh), _ptr(st), _ptr(ed), _ptr(ub),
-                                            _ptr(uw), _stream()))
+        _check(self.L.pd_macro_step_refresh(self.h, self._U(U_n, "U_n"), self._U(out, "U_np1"),
+                                            float(t_n), float(dt_macro), float(dt_micro),
+                                            int(n_t), int(n_refresh), self._state(st),
+                                            self._edge(ed), self._perpatch(ub),
+                                            self._U(uw, "U_work"), _stream()))
         return out
 
     def patch_step(self, U_n, t_n, out, dt_macro=None, dt_micro=None, n_t=None):
         t = self.prob["time"]
         _check(self.L.pd_patch_step(
-            self.h, _ptr(U_n), _ptr(out), float(t_n),
+            self.h, self._U(U_n, "U_n"), self._U(out, "U_np1"), float(t_n),
             float(t["dt_macro"] if dt_macro is None else dt_macro),
             float(t["dt_micro"] if dt_micro is None else dt_micro),
             int(t["n_t"] if n_t is None else n_t), _stream()))
@@ -450,7 +490,7 @@ class Grid:
         U = self.initial() if U is None else U
         best = C.c_double(0.0)
         _check(self.L.pd_autotune(
-            self.h, _ptr(U), float(t["t0"] if t_n is None else t_n),
+            self.h, self._U(U), float(t["t0"] if t_n is None else t_n),
             float(t["dt_macro"] if dt_macro is None else dt_macro),
             float(t["dt_micro"] if dt_micro is None else dt_micro),
             int(t["n_t"] if n_t is None else n_t), int(reps), TUNE_FORCE if force else 0,
@@ -458,13 +498,13 @@ class Grid:
         return best.value
 
     def apply_boundary(self, U, t):
-        _check(self.L.pd_apply_boundary(self.h, _ptr(U), float(t), _stream()))
+        _check(self.L.pd_apply_boundary(self.h, self._U(U), float(t), _stream()))
         return U
 
     def solve(self, U=None, n_steps=None, t0=None, dt_macro=None, dt_micro=None, n_t=None):
         t = self.prob["time"]
         U = self.initial() if U is None else U
-        _check(self.L.pd_solve(self.h, _ptr(U), float(t["t0"] if t0 is None else t0),
+        _check(self.L.pd_solve(self.h, self._U(U), float(t["t0"] if t0 is None else t0),
                                float(t["dt_macro"] if dt_macro is None else dt_macro),
                                int(t["n_steps"] if n_steps is None else n_steps),
                                float(t["dt_micro"] if dt_micro is None else dt_micro),
@@ -491,6 +531,7 @@ class Batch:
         arr = (BatchMember * n)()
         for i, (g, U) in enumerate(zip(self.grids, self.U)):
             t = g.prob["time"]
+            g._U(U, f"U of member {i}")
             arr[i] = BatchMember(g.h.value, U.data_ptr(), float(t["t0"]), float(t["dt_macro"]),
                                  float(t["dt_micro"]), int(t["n_t"]))
         self.h = C.c_void_p()
@@ -599,15 +640,19 @@ class FullDomain:
 
     def initial(self, t=0.0, U=None, stream=None):
         U = self.new_U() if U is None else U
-        _check(self.L.pd_fd_initial(self.h, _ptr(U), float(t), _stream(stream)))
+        _check(self.L.pd_fd_initial(self.h, self._U(U), float(t), _stream(stream)))
         return U
 
     def solve(self, U, t0, n_steps, stream=None):
-        _check(self.L.pd_fd_solve(self.h, _ptr(U), float(t0), int(n_steps), _stream(stream)))
+        _check(self.L.pd_fd_solve(self.h, self._U(U), float(t0), int(n_steps),
+                                  _stream(stream)))
         return U
 
     def sync(self, stream=None):
         _check(self.L.pd_fd_sync(self.h, _stream(stream)))
+
+    def _U(self, t, name="U"):
+        return _ptr(t, self.n_y * self.n_x, torch.float64, self.grid.device, name)
 
 
 N_FEAT, N_PARAMS = 33, 20993
@@ -637,6 +682,12 @@ class Closure:
             self.L.pd_closure_destroy(self.h)
             self.h = C.c_void_p()
 
+    def _X(self, t, n, name="X"):
+        return _ptr(t, n * N_FEAT, torch.float32, self.device, name)
+
+    def _y(self, t, n, name="y"):
+        return _ptr(t, n, torch.float32, self.device, name)
+
     def set_params(self, flat):
         a = self._np.ascontiguousarray(flat, dtype=self._np.float32)
         assert a.size == N_PARAMS
@@ -661,7 +712,8 @@ class Closure:
         return m, d
 
     def fit_standardisation(self, X, y=None):
-        _check(self.L.pd_closure_fit_standardisation(self.h, _ptr(X), _ptr(y), X.shape[0],
+        n = X.shape[0]
+        _check(self.L.pd_closure_fit_standardisation(self.h, self._X(X, n), self._y(y, n), n,
                                                      _stream()))
 
     def set_target_scale(self, mean, sd):
@@ -675,20 +727,25 @@ class Closure:
     def gradients(self, X, y):
         g = torch.empty(N_PARAMS, dtype=torch.float32, device=self.device)
         loss = torch.empty(1, dtype=torch.float32, device=self.device)
-        _check(self.L.pd_closure_gradients(self.h, _ptr(X), _ptr(y), X.shape[0], _ptr(g),
-                                           _ptr(loss), _stream()))
+        n = X.shape[0]
+        _check(self.L.pd_closure_gradients(self.h, self._X(X, n), self._y(y, n), n,
+                                           self._y(g, N_PARAMS, "grad"),
+                                           self._y(loss, 1, "loss"), _stream()))
         return g, loss
 
     def train(self, X, y, batch=4096, epochs=1, lr=1e-3, seed=0):
         losses = self._np.zeros(max(epochs, 1), dtype=self._np.float32)
-        _check(self.L.pd_closure_train(self.h, _ptr(X), _ptr(y), X.shape[0], batch, epochs,
+        n = X.shape[0]
+        _check(self.L.pd_closure_train(self.h, self._X(X, n), self._y(y, n), n, batch, epochs,
                                        float(lr), seed, losses.ctypes.data_as(C.c_void_p),
                                        _stream()))
         return losses[:epochs]
 
     def infer(self, X):
         out = torch.empty(X.shape[0], dtype=torch.float32, device=self.device)
-        _check(self.L.pd_closure_infer(self.h, _ptr(X), _ptr(out), X.shape[0], _stream()))
+        n = X.shape[0]
+        _check(self.L.pd_closure_infer(self.h, self._X(X, n), self._y(out, n, "out"), n,
+                                       _stream()))
         return out
 
     @staticmethod
@@ -696,22 +753,27 @@ class Closure:
         X = torch.empty((grid.P, N_FEAT), dtype=torch.float32, device=grid.device)
         F0 = torch.empty(grid.P, dtype=torch.float64, device=grid.device)
         s = torch.empty(grid.P, dtype=torch.float64, device=grid.device)
-        _check(grid.L.pd_closure_features(grid.h, _ptr(U), float(t_n), _ptr(X), _ptr(F0),
-                                          _ptr(s), _stream()))
+        _check(grid.L.pd_closure_features(
+            grid.h, grid._U(U), float(t_n),
+            _ptr(X, grid.P * N_FEAT, torch.float32, grid.device, "X"),
+            grid._perpatch(F0, "F0"), grid._perpatch(s, "s"), _stream()))
         return X, F0, s
 
     @staticmethod
     def targets(grid, U_n, U_np1, t_n, dt_macro, X=None, y=None):
         X = torch.empty((grid.P, N_FEAT), dtype=torch.float32, device=grid.device) if X is None else X
         y = torch.empty(grid.P, dtype=torch.float32, device=grid.device) if y is None else y
-        _check(grid.L.pd_closure_targets(grid.h, _ptr(U_n), _ptr(U_np1), float(t_n),
-                                         float(dt_macro), _ptr(X), _ptr(y), _stream()))
+        _check(grid.L.pd_closure_targets(
+            grid.h, grid._U(U_n, "U_n"), grid._U(U_np1, "U_np1"), float(t_n), float(dt_macro),
+            _ptr(X, grid.P * N_FEAT, torch.float32, grid.device, "X"),
+            _ptr(y, grid.P, torch.float32, grid.device, "y"), _stream()))
         return X, y
 
     def patch_step(self, grid, U_n, t_n, out=None, dt_macro=None, with_fhat=False):
         out = torch.empty_like(U_n) if out is None else out
         fh = torch.empty(grid.P, dtype=torch.float64, device=grid.device) if with_fhat else None
         dtm = grid.prob["time"]["dt_macro"] if dt_macro is None else dt_macro
-        _check(self.L.pd_closure_patch_step(self.h, grid.h, _ptr(U_n), _ptr(out), float(t_n),
-                                            float(dtm), _ptr(fh), _stream()))
+        _check(self.L.pd_closure_patch_step(self.h, grid.h, grid._U(U_n, "U_n"),
+                                            grid._U(out, "U_np1"), float(t_n), float(dtm),
+                                            grid._perpatch(fh, "F_hat"), _stream()))
         return (out, fh) if with_fhat else out

@@ -188,3 +188,48 @@ def test_core_points_validated(pd, core):
     d = pd.grid_desc(dict(prob["grid"], core=core))
     h = C.c_void_p()
     assert pd.lib().pd_create_grid(C.byref(d), C.byref(h)) == -1
+
+
+def test_binding_rejects_bad_tensors_before_the_library(pd, monkeypatch):
+    """The C ABI takes raw device pointers without lengths; the binding checks dtype,
+    layout, length and placement first and raises PD_EINVAL without calling the library
+    (a bad pointer would otherwise become an out-of-bounds device access)."""
+    import torch
+    g = _grid(pd, W.config2(n=9, m=5))
+    calls = []
+
+    real = g.L
+
+    class Spy:
+        def __getattr__(self, name):
+            def call(*a):
+                calls.append(name)
+                raise AssertionError(f"library reached: {name}")
+            return call
+
+    g.L = Spy()
+    P, me, mx, M = g.P, g.me, g.mx, g.M
+    state = torch.zeros((P, me, mx), dtype=torch.float64)
+    edge = torch.zeros((P, 4, M), dtype=torch.float64)
+    cases = [
+        ("dtype", state.float(), edge, "dtype"),
+        ("short", state[:-1], edge, "elements"),
+        ("strided", state.transpose(1, 2), edge, "contiguous"),
+        ("host", state, edge, "device tensor"),
+        ("not a tensor", state.numpy(), edge, "torch tensor"),
+    ]
+    try:
+        for label, st, ed, msg in cases:
+            with pytest.raises(pd.PdError) as ei:
+                g.micro_burst(st, ed, 0.0, 1e-6, 3)
+            assert ei.value.status == -1 and msg in str(ei.value), (label, str(ei.value))
+        U = torch.zeros((g.ne, g.nx), dtype=torch.float64)
+        with pytest.raises(pd.PdError, match="elements"):
+            g.solve(U[:-1])
+        with pytest.raises(pd.PdError, match="dtype"):
+            g.apply_boundary(U.float(), 0.0)
+        with pytest.raises(pd.PdError, match="device tensor"):
+            g.restrict(state)
+    finally:
+        g.L = real
+    assert not calls

@@ -498,12 +498,14 @@ void pdo_coeffs_at(const pdo_grid* g, const pdo_problem* pr, double xi, double e
 static double node_xi(const pdo_grid* g, int i) { return g->xi0 + i * dxi(g); }
 static double node_eta(const pdo_grid* g, int j) { return g->eta0 + j * deta(g); }
 
-void pdo_coefficients(const pdo_grid* g, const pdo_problem* pr, double* coef) {
+void pdo_coefficients_masked(const pdo_grid* g, const pdo_problem* pr,
+                             const unsigned char* mask, double* coef) {
   int P = pdo_num_patches(g), mx = g->m_xi, me = g->m_eta;
   int nc = PDO_NCOEF(pr);
   size_t plane = (size_t)P * mx * me;
   double out[5 + PDO_MAXTERM];
   for (int p = 0; p < P; ++p) {
+    if (mask && !mask[p]) continue;
     int i, j;
     patch_ij(g, p, &i, &j);
     for (int l = 0; l < me; ++l)
@@ -515,6 +517,10 @@ void pdo_coefficients(const pdo_grid* g, const pdo_problem* pr, double* coef) {
         for (int q = 0; q < nc; ++q) coef[q * plane + at] = out[q];
       }
   }
+}
+
+void pdo_coefficients(const pdo_grid* g, const pdo_problem* pr, double* coef) {
+  pdo_coefficients_masked(g, pr, NULL, coef);
 }
 
 static double sfun_value(const pdo_sfun* S, const mapv* m, double xi, double eta) {

@@ -124,6 +124,10 @@ void pdo_metric(const pdo_grid* g, double xi, double eta, double* out);
 void pdo_coeffs_at(const pdo_grid* g, const pdo_problem* prob, double xi, double eta, double* out);
 /* All coefficient planes at every micro point: layout [NCOEF][P][m_eta][m_xi]. */
 void pdo_coefficients(const pdo_grid* g, const pdo_problem* prob, double* coef);
+/* The same planes for the patches with mask[p] != 0 only (the others are left as they
+ * are): a sampled check of a large grid needs the coefficients of a few patches. */
+void pdo_coefficients_masked(const pdo_grid* g, const pdo_problem* prob,
+                             const unsigned char* mask, double* coef);
 /* u_b at one point and time. */
 double pdo_boundary_value(const pdo_grid* g, const pdo_problem* prob, double xi, double eta, double t);
 /* Macro field at t from u_b at every node; layout [n_eta][n_xi]. */

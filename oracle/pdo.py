@@ -100,6 +100,7 @@ def lib(extended=False):
             "pdo_metric": (None, [GP, C.c_double, C.c_double, _DP]),
             "pdo_coeffs_at": (None, [GP, PP, C.c_double, C.c_double, _DP]),
             "pdo_coefficients": (None, [GP, PP, _DP]),
+            "pdo_coefficients_masked": (None, [GP, PP, C.POINTER(C.c_ubyte), _DP]),
             "pdo_boundary_value": (C.c_double, [GP, PP, C.c_double, C.c_double, C.c_double]),
             "pdo_initial": (None, [GP, PP, C.c_double, _DP]),
             "pdo_edge": (None, [GP, _DP, _DP]),
@@ -254,6 +255,17 @@ class Oracle:
             self.L.pdo_coefficients(self.G, self.Pp, _dp(c))
             self._coef = c
         return self._coef
+
+    def coefficients_for(self, mask):
+        """Fill the coefficient planes of the patches with mask[p] set only (zeros
+        elsewhere): enough for steps restricted to those patches on a large grid."""
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert mk.shape == (self.P,)
+        c = np.zeros((self.ncoef, self.P, self.me, self.mx))
+        self.L.pdo_coefficients_masked(self.G, self.Pp, mk.ctypes.data_as(C.POINTER(C.c_ubyte)),
+                                       _dp(c))
+        self._coef = c
+        return c
 
     def boundary_value(self, xi, eta, t):
         return self.L.pdo_boundary_value(self.G, self.Pp, float(xi), float(eta), float(t))

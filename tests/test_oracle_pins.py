@@ -736,3 +736,16 @@ def test_core_size_validated(oracle_mod):
         p["grid"]["core"] = core
         with pytest.raises(Exception):
             make(oracle_mod, p)
+
+
+def test_masked_coefficients_equal_the_full_planes(oracle_mod):
+    """The sampled checks of large grids fill only the patches they step: those planes
+    equal the full construction bit for bit, the others stay zero."""
+    p = W.config3(n_r=9, n_theta=16, m=7)
+    full = make(oracle_mod, p).coef
+    o = make(oracle_mod, p)
+    mask = np.zeros(o.P, dtype=np.uint8)
+    mask[[0, 5, o.P - 1]] = 1
+    c = o.coefficients_for(mask)
+    assert c[:, mask == 1].tobytes() == full[:, mask == 1].tobytes()
+    assert not np.any(c[:, mask == 0])

@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
-"""Throughput of the fused patch-dynamics macro step (Sec. 3.3 steps (i)-(vi)) on one GPU.
+"""Throughput of the patch-dynamics hot path (Sec. 3.3 steps (i)-(vi)) on one GPU.
 
-A step is one macro step of the whole hot path over the full workload: edge data, lifting,
-the forward-Euler burst in every patch, restriction and the projective update, plus the
-Dirichlet boundary, replayed from a HIP graph.  Default workload: the stretched unit square
-(tanh stretching, 65x65 macro nodes, 17x17 micro points per patch, random Fourier-mode
-coefficients) in FP64.  Prints one JSON line.
+Default (--workload headline): the metric's pairing in one JSON line.  The plain batched
+scheme in FP64 on the mixed batch of 512 seeded instances (tanh-stretched squares and
+annuli, 17..129 macro nodes per side, 9..33 micro points per patch side), one persistent
+launch per batch macro step replayed from a HIP graph, is the line's value (patch-point
+updates/s, with macro steps/s and the k_batch roofline); the same batch with the learned
+closure standing in for the bursts (1% spot checks, per-member fallback) reports its
+macro steps/s, the speed-up over plain and its relative L2 error against the plain run,
+also over a long horizon on held-out members.  The CPU baseline is the FP64 oracle on a
+seeded sample of the batch, on all host cores and on one thread.
 
-Other workloads (--workload): config1 and config3 (the same fused step on the small square
-and the annulus), config4 (the batched persistent form), config5 (the learned closure),
-full-domain (the explicit comparator on one fine lattice), refresh (edge data refreshed
-between sub-bursts), adi (the ADI micro solver on the Sec. 4.1.1 setup) and upwind (the
-3- or 4-point upwind micro differences on the config 2 problem).
+Other workloads (--workload): config1, config2 and config3 (the fused single-grid step
+on the small square, the stretched square in FP64 or FP32, the annulus), config4 (the
+batch alone), config5 (the closure line), full-domain (the explicit comparator on one fine
+lattice), refresh (edge data refreshed between sub-bursts), adi (the ADI micro solver on
+the Sec. 4.1.1 setup) and upwind (the 3- or 4-point upwind micro differences on the
+config 2 problem).
 """
 import argparse
 import json
@@ -149,167 +154,333 @@ def cpu_baseline(prob, budget_s, steps_cap):
             "macro_steps_per_s": done / el}
 
 
-def bench_batch(args):
-    """The mixed batch: every instance advances one macro step per persistent launch."""
-    import torch
+BATCH_SOURCES = ["pd_batch.hip", "pd_burst.inc", "pd_internal.h"]
+CLOSURE_SOURCES = ["pd_closure.hip", "pd_internal.h"]
 
+
+def host_info():
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cpu_count": os.cpu_count(), "host_cpu_model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_threads():
+    """Threads for the all-cores leg: the host's cores, capped by OMP_NUM_THREADS (the
+    CPU share a one-GPU job is given)."""
+    n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return n
+
+
+def batch_cpu_baseline(probs, per_step_updates, budget_s, threads, patches=256, seed=1):
+    """The FP64 oracle on a bounded sample of the mixed batch: seeded members in a seeded
+    order, each advancing `patches` seeded patches (all of a smaller member) through one
+    whole macro step (edge data, lift, burst, restriction, projection); coefficient
+    planes of those patches are built before the clock starts.  Returns the rate and the
+    batch macro steps/s it implies (the full batch's updates per step at that rate)."""
+    import numpy as np
+    from oracle import pdo
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(len(probs))
+    done_updates, el, used, members = 0, 0.0, 0, 0
+    for i in order:
+        if el >= budget_s:
+            break
+        p = probs[i]
+        o = pdo.Oracle(p, threads=threads)
+        k = min(patches, o.P)
+        mask = np.zeros(o.P, dtype=np.uint8)
+        mask[rng.choice(o.P, size=k, replace=False)] = 1
+        o.coefficients_for(mask)
+        U = o.initial()
+        t = p["time"]
+        s = time.perf_counter()
+        o.step(U, t["t0"], mask=mask)
+        el += time.perf_counter() - s
+        done_updates += k * o.mx * o.me * t["n_t"]
+        used = o.L.pdo_get_threads()
+        members += 1
+    rate = done_updates / el
+    return {"value": rate, "unit": "patch-point updates/s", "cores": used, "kind": "oracle",
+            "sample": f"{members} seeded members of the batch, up to {patches} seeded patches "
+                      f"each, one whole macro step each: {done_updates:.3e} updates in "
+                      f"{el:.1f} s",
+            "batch_macro_steps_per_s_at_this_rate": rate / per_step_updates}
+
+
+def make_batch(n_instances, n_steps, shapes_path=None, log=None):
+    """The mixed batch (time parameters at 0.4 of each member's explicit bounds) with its
+    launch shapes: read from shapes_path when that file exists, else autotuned (and
+    written there).  Returns (probs, grids, batch, tuned_ms or None)."""
     from paper_2405_08764_amd import pd
     from paper_2405_08764_amd import workloads as W
-    torch.cuda.set_device(0)
-    stream = torch.cuda.Stream()
-    t_setup = time.perf_counter()
-    with torch.cuda.stream(stream):
-        grids = []
-        for p in W.config4(args.instances):
-            g = pd.Grid(p)
-            info = g.query()
-            g.prob = W.fit_time(p, info.dt_macro_limit, info.dt_micro_limit, args.steps)
-            grids.append(g)
-        B = pd.Batch(grids)
-        untuned = B.query()
+    probs, grids = [], []
+    for p in W.config4(n_instances):
+        g = pd.Grid(p)
+        info = g.query()
+        g.prob = W.fit_time(p, info.dt_macro_limit, info.dt_micro_limit, n_steps)
+        probs.append(g.prob)
+        grids.append(g)
+    B = pd.Batch(grids)
+    tuned_ms = None
+    if shapes_path and os.path.exists(shapes_path):
+        with open(shapes_path) as fh:
+            shapes = json.load(fh)
+        assert len(shapes) == len(grids), "shape file is for another batch"
+        for i, sh in enumerate(shapes):
+            B.set_shape(i, int(sh))
+        if log:
+            log(f"launch shapes read from {shapes_path}")
+    else:
         tuned_ms = B.autotune(reps=2)
-        binfo = B.query()
-        print(f"[bench] batch of {len(grids)}: {binfo.n_items} items, {binfo.blocks} blocks, "
-              f"setup {time.perf_counter() - t_setup:.1f} s", file=sys.stderr, flush=True)
-        B.solve(max(args.warmup // 8, 2))
-        B.sync()
-        torch.cuda.synchronize()
-        s = time.perf_counter()
-        B.solve(args.steps)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - s
-        B.sync()
+        if shapes_path:
+            with open(shapes_path, "w") as fh:
+                json.dump([B.shape(i)[0] for i in range(len(grids))], fh)
+    return probs, grids, B, tuned_ms
+
+
+def reset_fields(grids, B):
+    for g, U in zip(grids, B.U):
+        g.initial(U=U)
+
+
+def time_batch(B, grids, warmup, steps, stream, closure=False):
+    """`warmup` untimed batch macro steps from the initial data, then the initial data
+    again and `steps` timed steps (HIP events on the launch stream, and the host clock
+    around synchronisations).  Returns (seconds, event seconds)."""
+    import torch
+    run = B.closure_solve if closure else B.solve
+    reset_fields(grids, B)
+    if warmup:
+        run(warmup)
+    torch.cuda.synchronize()
+    reset_fields(grids, B)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s = time.perf_counter()
+    a.record(stream)
+    run(steps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - s
+    B.sync()
+    return el, a.elapsed_time(b) / 1e3
+
+
+def batch_line(grids, B, tuned_ms, el, ev_s, args, untuned_items=None):
+    """The plain batch part of a JSON line: rates, shapes and the k_batch roofline."""
+    from paper_2405_08764_amd import pd
+    binfo = B.query()
     per_step = binfo.updates_per_step
     shapes = {}
     for i in range(len(grids)):
         sh, ppb = B.shape(i)
-        key = f"m={grids[i].mx}"
-        shapes.setdefault(key, set()).add(f"{pd.BATCH_MENU[sh]}x{ppb}")
-    achieved = 20 * per_step / (tuned_ms * 1e-3)
+        shapes.setdefault(f"m={grids[i].mx}", set()).add(f"{pd.BATCH_MENU[sh]}x{ppb}")
+    kern_s = ev_s / args.steps  # one k_batch launch per step (+ a table fill every 16)
+    achieved = 20 * per_step / kern_s
     peak = PEAK["f64"]
-    P = sum(g.P for g in grids)
-    pts = sum(g.P * g.mx * g.me for g in grids)
     n_ts = [g.prob["time"]["n_t"] for g in grids]
+    traffic = read_traffic("k_batch", "config4", "f64", "tuned", BATCH_SOURCES)
+    cfg = {"patches": sum(g.P for g in grids),
+           "micro_points": sum(g.P * g.mx * g.me for g in grids),
+           "updates_per_step": per_step, "n_t_range": [min(n_ts), max(n_ts)],
+           "items": binfo.n_items, "blocks": binfo.blocks, "lds_bytes": binfo.lds_bytes,
+           "shapes": {k: sorted(v) for k, v in sorted(shapes.items())},
+           "autotune_ms": tuned_ms}
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "kernel": "k_batch (persistent, one batch macro step per launch)",
+            "kernel_ms": kern_s * 1e3, "flops_per_update": 20,
+            "issued_flops_per_update": 12,
+            "issued_frac": 12 * per_step / kern_s / peak}
+    return per_step, cfg, roof
+
+
+def bench_batch(args):
+    """The mixed batch alone: every instance advances one macro step per persistent
+    launch."""
+    import torch
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        t0 = time.perf_counter()
+        probs, grids, B, tuned_ms = make_batch(args.instances, args.steps, args.batch_shapes,
+                                               log)
+        log(f"batch of {len(grids)} ready in {time.perf_counter() - t0:.1f} s")
+        el, ev_s = time_batch(B, grids, args.warmup, args.steps, stream)
+    per_step, cfg, roof = batch_line(grids, B, tuned_ms, el, ev_s, args)
     out = {
         "metric": "patch-point updates/s (and macro steps/s) of the batched plain scheme",
-        "value": per_step * args.steps / el,
-        "unit": "patch-point updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": max(args.warmup // 8, 2),
-        "ms_per_step": el / args.steps * 1e3,
-        "macro_steps_per_s": args.steps / el,
+        "value": per_step * args.steps / el, "unit": "patch-point updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "macro_steps_per_s": args.steps / el,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded analytic coefficients, no dataset)",
-        "config": {"workload": f"config4: {len(grids)} mixed instances (tanh squares and "
-                               "annuli, N 17..129, m 9..33, Fourier D and v, eps "
-                               "1e-3..1e-2, reaction 0..2), one persistent launch per step",
-                   "patches": P, "micro_points": pts, "updates_per_step": per_step,
-                   "n_t_range": [min(n_ts), max(n_ts)], "items": binfo.n_items,
-                   "blocks": binfo.blocks, "lds_bytes": binfo.lds_bytes,
-                   "untuned_items": untuned.n_items,
-                   "shapes": {k: sorted(v) for k, v in sorted(shapes.items())}},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_batch (persistent, one batch macro step)",
-                     "kernel_ms": tuned_ms, "flops_per_update": 20},
+        "config": dict({"workload": f"config4: {len(grids)} mixed instances (tanh squares "
+                                    "and annuli, N 17..129, m 9..33, Fourier D and v, eps "
+                                    "1e-3..1e-2, reaction 0..2), one persistent launch per "
+                                    "step"}, **cfg),
+        "roofline": roof,
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = batch_cpu_baseline(probs, per_step, args.cpu_seconds,
+                                                 oracle_threads())
+        out["cpu_baseline"].update(host_info())
     print(json.dumps(out), flush=True)
 
 
-def bench_closure(args):
-    """The mixed batch with the learned closure standing in for the micro-bursts (1% of
-    the work items re-run by the plain scheme each step as spot checks, per-member
-    fallback), against the plain batched scheme on the same batch."""
+def closure_part(args, B, grids, stream, t_plain, ref, log):
+    """Train the closure on plain-scheme pairs of disjoint instances and time the batch
+    with it (spot checks on 1% of the work items per step, per-member fallback): rates,
+    error against the plain batch over the same steps, and the baseline operator alone."""
+    import numpy as np
+    import torch
+
+    from paper_2405_08764_amd import closure_train as T
+    N = args.steps
+    s = time.perf_counter()
+    tg = T.instance_grids(args.train_instances, T.TRAIN_SEED, 40)
+    X, y = T.generate(tg, steps=16, every=2, max_pairs=args.train_pairs)
+    n_pairs = int(X.shape[0])
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - s
+    s = time.perf_counter()
+    C, losses = T.train(X, y, epochs=args.epochs, batch=4096, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - s
+    ym, ysd = C.target_scale()
+    rms = float(np.sqrt(losses[-1])) * ysd  # residual RMS in units of s
+    threshold = args.threshold_factor * rms
+    log(f"pairs {n_pairs} generated in {t_gen:.1f} s, trained in {t_train:.1f} s, "
+        f"loss {losses[0]:.4g} -> {losses[-1]:.4g}, threshold {threshold:.3g}")
+    del tg, X, y
+    B.attach_closure(C, stride=100, threshold=threshold)
+    B.closure_stats(reset=True)
+    t_cl, ev_cl = time_batch(B, grids, args.warmup, N, stream, closure=True)
+    checked, fallbacks = B.closure_stats()
+    # the warm-up steps are counted too: report the timed steps' share
+    errs = np.array([T.rel_l2(a, b) for a, b in zip(B.U, ref)])
+    Z = T.zero_closure(C)
+    B.attach_closure(Z, stride=100, threshold=1e30)
+    reset_fields(grids, B)
+    B.closure_solve(N)
+    torch.cuda.synchronize()
+    errs0 = np.array([T.rel_l2(a, b) for a, b in zip(B.U, ref)])
+    P = sum(g.P for g in grids)
+    part = {
+        "macro_steps_per_s": N / t_cl, "ms_per_step": t_cl / N * 1e3,
+        "speedup_vs_plain": t_plain / t_cl,
+        "rel_l2_vs_plain": {"steps": N, "max": float(errs.max()), "mean": float(errs.mean())},
+        "rel_l2_baseline_operator_only": {"max": float(errs0.max()),
+                                          "mean": float(errs0.mean())},
+        "spot_checks": {"patches_checked": checked,
+                        "fraction": checked / (P * (N + args.warmup)),
+                        "member_fallbacks": fallbacks, "threshold": threshold},
+        "training": {"pairs": n_pairs, "epochs": args.epochs,
+                     "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                     "generate_s": t_gen, "train_s": t_train},
+        "dtype": "bf16 MFMA (fp32 accumulate) closure, f64 plain fallback",
+    }
+    return C, threshold, part
+
+
+def closure_horizon(args, C, threshold, log):
+    """The closure against the plain scheme over a long horizon on held-out members (the
+    first members of the evaluation batch; training used other seeds)."""
     import numpy as np
     import torch
 
     from paper_2405_08764_amd import closure_train as T
     from paper_2405_08764_amd import pd
     from paper_2405_08764_amd import workloads as W
+    n, H = args.horizon_members, args.horizon_steps
+    grids = T.instance_grids(n, W.MASTER_SEED + 4000, H)
+    U0 = [g.initial() for g in grids]
+    B = pd.Batch(grids, [u.clone() for u in U0])
+    B.autotune(reps=1)
+    s = time.perf_counter()
+    B.solve(H)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - s
+    ref = [u.clone() for u in B.U]
+    for u, u0 in zip(B.U, U0):
+        u.copy_(u0)
+    B.attach_closure(C, stride=100, threshold=threshold)
+    B.closure_stats(reset=True)
+    s = time.perf_counter()
+    B.closure_solve(H)
+    torch.cuda.synchronize()
+    t_cl = time.perf_counter() - s
+    checked, fallbacks = B.closure_stats()
+    errs = np.array([T.rel_l2(a, b) for a, b in zip(B.U, ref)])
+    log(f"horizon {H} steps on {n} members: max {errs.max():.3g}, mean {errs.mean():.3g}")
+    return {"members": n, "steps": H, "max": float(errs.max()), "mean": float(errs.mean()),
+            "member_fallbacks": fallbacks, "plain_s": t_plain, "closure_s": t_cl}
+
+
+def bench_closure(args):
+    """The mixed batch with the learned closure standing in for the micro-bursts, against
+    the plain batched scheme on the same batch."""
+    return bench_headline(args, workload_name="config5")
+
+
+def bench_headline(args, workload_name="config4+config5"):
+    """The metric's pairing on one GPU: the plain batched scheme (config 4, FP64) and the
+    same batch with the learned closure (config 5), in one line."""
+    import torch
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-    N = args.steps
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
     with torch.cuda.stream(stream):
-        t_setup = time.perf_counter()
-        grids = T.instance_grids(args.instances, W.MASTER_SEED + 4000, N)
-        U0 = [g.initial() for g in grids]
-        B = pd.Batch(grids, [u.clone() for u in U0])
-        B.autotune(reps=2)
-        log(f"batch of {len(grids)} ready in {time.perf_counter() - t_setup:.1f} s")
-        # plain scheme
-        B.solve(2)
-        torch.cuda.synchronize()
-        for u, u0 in zip(B.U, U0):
-            u.copy_(u0)
-        torch.cuda.synchronize()
-        s = time.perf_counter()
-        B.solve(N)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - s
+        t0 = time.perf_counter()
+        probs, grids, B, tuned_ms = make_batch(args.instances, args.steps, args.batch_shapes,
+                                               log)
+        log(f"batch of {len(grids)} ready in {time.perf_counter() - t0:.1f} s")
+        el, ev_s = time_batch(B, grids, args.warmup, args.steps, stream)
         ref = [u.clone() for u in B.U]
-        log(f"plain: {N / t_plain:.3f} batch steps/s")
-        # training pairs from plain steps of disjoint instances, training
-        s = time.perf_counter()
-        tg = T.instance_grids(args.train_instances, T.TRAIN_SEED, 40)
-        X, y = T.generate(tg, steps=16, every=2, max_pairs=args.train_pairs)
-        n_pairs = int(X.shape[0])
-        torch.cuda.synchronize()
-        t_gen = time.perf_counter() - s
-        s = time.perf_counter()
-        C, losses = T.train(X, y, epochs=args.epochs, batch=4096, lr=2e-3)
-        torch.cuda.synchronize()
-        t_train = time.perf_counter() - s
-        ym, ysd = C.target_scale()
-        rms = float(np.sqrt(losses[-1])) * ysd  # residual RMS in units of s
-        threshold = args.threshold_factor * rms
-        log(f"pairs {X.shape[0]} generated in {t_gen:.1f} s, trained in {t_train:.1f} s, "
-            f"loss {losses[0]:.4g} -> {losses[-1]:.4g}, threshold {threshold:.3g}")
-        del tg, X, y
-        # closure scheme
-        B.attach_closure(C, stride=100, threshold=threshold)
-        B.closure_solve(2)
-        torch.cuda.synchronize()
-        for u, u0 in zip(B.U, U0):
-            u.copy_(u0)
-        B.closure_stats(reset=True)
-        torch.cuda.synchronize()
-        s = time.perf_counter()
-        B.closure_solve(N)
-        torch.cuda.synchronize()
-        t_cl = time.perf_counter() - s
-        checked, fallbacks = B.closure_stats()
-        errs = np.array([T.rel_l2(a, b) for a, b in zip(B.U, ref)])
-        # the baseline operator alone, for what the network adds
-        Z = T.zero_closure(C)
-        for u, u0 in zip(B.U, U0):
-            u.copy_(u0)
-        B.attach_closure(Z, stride=100, threshold=1e30)
-        B.closure_solve(N)
-        torch.cuda.synchronize()
-        errs0 = np.array([T.rel_l2(a, b) for a, b in zip(B.U, ref)])
-    info = B.query()
-    P = sum(g.P for g in grids)
+        log(f"plain: {args.steps / el:.3f} batch steps/s")
+        C, threshold, surrogate = closure_part(args, B, grids, stream, el, ref, log)
+        if args.horizon_steps > 0:
+            surrogate["rel_l2_vs_plain_long_horizon"] = closure_horizon(args, C, threshold,
+                                                                        log)
+    per_step, cfg, roof = batch_line(grids, B, tuned_ms, el, ev_s, args)
     out = {
-        "metric": "macro steps/s of the batched scheme with the learned closure vs plain",
-        "value": N / t_cl,
-        "unit": "batch macro steps/s",
-        "n_gpus": 1, "steps": N, "warmup": 2, "ms_per_step": t_cl / N * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 MFMA (fp32 accumulate) closure, f64 plain fallback",
+        "metric": "patch-point updates/s + macro steps/s at fixed L2 err; surrogate vs "
+                  "plain GPU",
+        "value": per_step * args.steps / el, "unit": "patch-point updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "macro_steps_per_s": args.steps / el,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded analytic coefficients, no dataset)",
-        "config": {"workload": f"config5: learned closure on the config4 batch of "
-                               f"{len(grids)} instances, 1% spot checks per step",
-                   "patches": P, "updates_per_step_plain": info.updates_per_step},
-        "plain_macro_steps_per_s": N / t_plain,
-        "speedup_vs_plain": t_plain / t_cl,
-        "rel_l2_vs_plain": {"max": float(errs.max()), "mean": float(errs.mean())},
-        "rel_l2_baseline_operator_only": {"max": float(errs0.max()), "mean": float(errs0.mean())},
-        "spot_checks": {"patches_checked": checked, "fraction": checked / (P * N),
-                        "member_fallbacks": fallbacks, "threshold": threshold},
-        "training": {"pairs": n_pairs, "epochs": args.epochs,
-                     "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
-                     "generate_s": t_gen, "train_s": t_train},
+        "config": dict({"workload": f"{workload_name}: plain batched scheme (FP64) on "
+                                    f"{len(grids)} mixed instances (tanh squares and annuli, "
+                                    "N 17..129, m 9..33, Fourier D and v, eps 1e-3..1e-2, "
+                                    "reaction 0..2), one persistent launch per step; and the "
+                                    "same batch with the learned closure (bf16 MFMA MLP "
+                                    "33-128-128-1, 1% spot checks, per-member fallback)"},
+                       **cfg),
+        "roofline": roof,
+        "surrogate": surrogate,
     }
+    if not args.no_cpu_baseline:
+        cb = batch_cpu_baseline(probs, per_step, args.cpu_seconds, oracle_threads())
+        one = batch_cpu_baseline(probs, per_step, args.cpu_seconds_one, 1, patches=32)
+        cb["one_thread"] = {k: one[k] for k in ("value", "cores", "sample",
+                                                "batch_macro_steps_per_s_at_this_rate")}
+        cb.update(host_info())
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 
@@ -330,7 +501,7 @@ def bench_refresh(args):
         g = pd.Grid(prob)
         U = g.initial()
         V = g.new_U()
-        for s in range(4):
+        for s in range(args.warmup):
             g.macro_step_refresh(U, t["t0"] + s * t["dt_macro"], Q, out=V)
             U, V = V, U
         g.sync()
@@ -375,7 +546,7 @@ def bench_refresh(args):
         "metric": "patch-point updates/s (and macro steps/s) with the edge data refreshed "
                   "during the burst",
         "value": per_step * K / el, "unit": "patch-point updates/s",
-        "n_gpus": 1, "steps": K, "warmup": 4, "ms_per_step": el / K * 1e3,
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": el / K * 1e3,
         "macro_steps_per_s": K / el,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded analytic coefficients, no dataset)",
@@ -435,7 +606,7 @@ def bench_adi(args):
                                 Ubar=g.restrict(state))
 
         U = g.initial()
-        for s in range(4):
+        for s in range(args.warmup):
             U = step(U, s * dtm)
         g.sync()
         U = g.initial()
@@ -465,7 +636,7 @@ def bench_adi(args):
     out = {
         "metric": "patch-point updates/s of the ADI micro burst (Sec. 4.1.1 setup)",
         "value": pts * n_t * K / el, "unit": "patch-point updates/s",
-        "n_gpus": 1, "steps": K, "warmup": 4, "ms_per_step": el / K * 1e3,
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": el / K * 1e3,
         "macro_steps_per_s": K / el,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (the paper's analytic coefficients, no dataset)",
@@ -528,7 +699,7 @@ def bench_upwind(args):
                                 Ubar=g.restrict(state))
 
         U = g.initial()
-        for s in range(4):
+        for s in range(args.warmup):
             U = step(U, s * dtm)
         g.sync()
         U = g.initial()
@@ -576,7 +747,7 @@ def bench_upwind(args):
     out = {
         "metric": "patch-point updates/s of the higher-order upwind micro burst",
         "value": pts * n_t * K / el, "unit": "patch-point updates/s",
-        "n_gpus": 1, "steps": K, "warmup": 4, "ms_per_step": el / K * 1e3,
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": el / K * 1e3,
         "macro_steps_per_s": K / el,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded random Fourier coefficients, no dataset)",
@@ -732,12 +903,25 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed macro steps (default 1000; 10 for config4, 20 for config5)")
-    ap.add_argument("--warmup", type=int, default=32)
+                    help="timed macro steps (default 20 for the headline, config4 and "
+                         "config5; 1000 for config1-3)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed macro steps run just before the timed ones (default 3 "
+                         "for the batch workloads, 32 for config1-3, 4 otherwise)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config3", "config4", "config5",
-                             "full-domain", "refresh", "adi", "upwind"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "config1", "config2", "config3", "config4",
+                             "config5", "full-domain", "refresh", "adi", "upwind"])
+    ap.add_argument("--batch-shapes", default=None, metavar="JSON",
+                    help="config4/5 and headline: read the batch launch shapes from this "
+                         "file if it exists (no autotuning), else autotune and write it")
+    ap.add_argument("--horizon-steps", type=int, default=200,
+                    help="headline/config5: closure error against plain over this many "
+                         "steps on held-out members (0: skip)")
+    ap.add_argument("--horizon-members", type=int, default=64,
+                    help="headline/config5: members of that long-horizon comparison")
+    ap.add_argument("--cpu-seconds-one", type=float, default=8.0,
+                    help="headline: budget of the one-thread oracle leg")
     ap.add_argument("--adi-n", type=int, default=129,
                     help="adi: macro nodes per side")
     ap.add_argument("--upwind-points", type=int, default=3, choices=[2, 3, 4],
@@ -779,8 +963,13 @@ def main():
     ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = {"config4": 10, "config5": 20, "full-domain": 400,
+        args.steps = {"headline": 20, "config4": 20, "config5": 20, "full-domain": 400,
                       "refresh": 200, "adi": 200, "upwind": 200}.get(args.workload, 1000)
+    if args.warmup is None:
+        args.warmup = {"headline": 3, "config4": 3, "config5": 3, "config1": 32,
+                       "config2": 32, "config3": 32}.get(args.workload, 4)
+    if args.warmup < 0 or args.steps < 1:
+        ap.error("--steps must be >= 1 and --warmup >= 0")
     if args.pmc_summary:
         if args.workload == "full-domain":
             pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_fd_step",
@@ -811,6 +1000,8 @@ def main():
     from paper_2405_08764_amd import pd
     from paper_2405_08764_amd import workloads as W
 
+    if args.workload == "headline":
+        return bench_headline(args)
     if args.workload == "config4":
         return bench_batch(args)
     if args.workload == "config5":
@@ -839,13 +1030,17 @@ def main():
             g.set_option(pd.OPT_PATCHES_PER_BLOCK, ppb)
         elif not args.no_autotune:
             tuned_ms = g.autotune(U, reps=5)
-        g.solve(U, n_steps=max(args.warmup, 16))
+        # set-up: one graph replay (16 steps) instantiates the solve graph on this field
+        g.solve(U, n_steps=16)
+        g.sync()
+        g.initial(U=U)
+        # exactly `warmup` untimed steps, then the timed steps continue from there
+        g.solve(U, n_steps=args.warmup)
         g.sync()
         per_step = W.updates_per_step(prob)
-        U = g.initial()
         torch.cuda.synchronize()
         s = time.perf_counter()
-        g.solve(U, n_steps=args.steps)
+        g.solve(U, n_steps=args.steps, t0=t["t0"] + args.warmup * t["dt_macro"])
         torch.cuda.synchronize()
         el = time.perf_counter() - s
         g.sync()
@@ -896,7 +1091,8 @@ def main():
         "unit": "patch-point updates/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": max(args.warmup, 16),
+        "warmup": args.warmup,
+        "setup_steps": 16,
         "ms_per_step": el / args.steps * 1e3,
         "macro_steps_per_s": args.steps / el,
         "higher_is_better": True,

@@ -819,8 +819,11 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
   // Macro steps per graph replay: one k_replay node (clock, time factors and Dirichlet
   // values of all S steps), then one fused burst per step.
   const size_t per = (size_t)g->src.ns * n_t;
-  int S = n_steps < MAX_REPLAY ? n_steps : MAX_REPLAY;
+  // Graph replays are always S steps long; a shorter request, or the remainder of a
+  // longer one, runs as direct launches, so short runs (warm-ups) never rebuild the graph.
+  int S = MAX_REPLAY;
   while (S > 1 && S * per > TT_CAP) --S;
+  const int reps = n_steps / S, rem = n_steps - reps * S;
   const int nb = boundary_count(g->g);
   a.nb = nb;
   const bool reuse = g->gexec && g->g_steps == S && g->g_dtm == dt_macro && g->g_dt == dt &&
@@ -844,7 +847,7 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     }
     return e;
   };
-  if (!reuse) {
+  if (reps > 0 && !reuse) {
     drop_graph(g);
     HIPCHK(hipStreamBeginCapture(w, hipStreamCaptureModeThreadLocal));
     const hipError_t e = steps(S);
@@ -867,7 +870,6 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     g->g_threads = g->threads;
     g->g_xch = g->xch;
   }
-  const int reps = n_steps / S, rem = n_steps - reps * S;
   for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(g->gexec, w));
   if (rem) HIPCHK(steps(rem));
   if (n_steps & 1)

@@ -387,6 +387,23 @@ pd_status pd_closure_targets(pd_grid g, const double* U_n, const double* U_np1, 
  * parameters) on n <= max_batch rows of raw inputs X and targets y. */
 pd_status pd_closure_gradients(pd_closure c, const float* X, const float* y, int32_t n,
                                float* grad, float* loss, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * training loops, harnesses that forbid hipMalloc): pd_closure_gradients with its scratch
+ * (standardised rows, activations, back-propagated planes, split-K partial sums) in a
+ * fixed device array inside the library instead of the closure workspace's training
+ * buffers.  Same kernels and arguments; grad [20993] and loss [1] (FP32, device) must be
+ * non-null and are written directly (loss is cleared by a kernel, no memset).  Limit:
+ * 1 <= n <= PD_NOALLOC_MAX_ROWS rows, else PD_EINVAL with a message; the closure must
+ * have its workspace bound, parameters and standardisation set (PD_ESTATE otherwise).
+ * The array takes pd_noalloc_scratch_bytes() (about 17 MB) on each device the library
+ * runs on, held until the process ends.  The call allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine.  Every call on one device shares that device's
+ * array, so calls that overlap on one device (other streams, other threads) race; calls
+ * ordered on one stream are safe. */
+#define PD_NOALLOC_MAX_ROWS 4096
+pd_status pd_closure_gradients_noalloc(pd_closure c, const float* X, const float* y, int32_t n,
+                                       float* grad, float* loss, void* stream);
+size_t pd_noalloc_scratch_bytes(void);
 /* `epochs` passes over n rows in minibatches of `batch` rows (a seeded affine shuffle per
  * epoch, n / batch full batches), one Adam step each; host_losses (may be NULL) receives
  * the mean minibatch loss of each epoch (then the call synchronises per epoch). */

@@ -282,6 +282,12 @@ __global__ void k_colsums(int n, const float* __restrict__ dH1, const float* __r
   }
 }
 
+// x[e] = v for e < n (a kernel, not a memset: safe inside captured graphs).
+__global__ void k_fill_f32(float* __restrict__ x, long long n, float v) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = v;
+}
+
 // Adam on the flat parameter vector (FP32 master weights); step counts from 1.
 __global__ void k_adam(float* __restrict__ par, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, int step, float lr, float b1, float b2,
@@ -633,6 +639,12 @@ hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float
   hipLaunchKernelGGL(k_gelu_back, dim3(eb), blk, 0, s, nb, dH1, H1);
   gemm_tn_split(CL_FEAT, CL_HID, Xn, CL_FEAT, dH1, CL_HID, grad + CL_OW1);
   hipLaunchKernelGGL(k_colsums, dim3(CL_HID + 1), blk, 0, s, nb, dH1, dH2, A2, dout, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* x, long long n, float v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, v);
   return hipGetLastError();
 }
 

@@ -349,6 +349,7 @@ hipError_t launch_mlp_grads(int nb, const float* Xn, const float* y, const float
                             float* part, hipStream_t s);
 hipError_t launch_adam(float* par, float* m, float* v, const float* g, int step, float lr,
                        hipStream_t s);
+hipError_t launch_fill_f32(float* x, long long n, float v, hipStream_t s);
 hipError_t launch_colstats(long long n, const float* X, float* mu, float* sd, hipStream_t s);
 hipError_t launch_standardise(long long n, const float* X, long long n_src, long long a,
                               long long c, const float* mu, const float* sd, float* Xn,

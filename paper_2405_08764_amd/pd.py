@@ -170,6 +170,10 @@ EXPORTS = {
                                        C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_closure_gradients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pd_closure_gradients_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                                 C.c_int32, C.c_void_p, C.c_void_p,
+                                                 C.c_void_p]),
+    "pd_noalloc_scratch_bytes": (C.c_size_t, []),
     "pd_closure_train": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                      C.c_int32, C.c_float, C.c_uint32, C.c_void_p,
                                      C.c_void_p]),
@@ -656,6 +660,7 @@ class FullDomain:
 
 
 N_FEAT, N_PARAMS = 33, 20993
+NOALLOC_MAX_ROWS = 4096  # PD_NOALLOC_MAX_ROWS of include/pd.h
 
 
 class Closure:
@@ -732,6 +737,15 @@ class Closure:
                                            self._y(g, N_PARAMS, "grad"),
                                            self._y(loss, 1, "loss"), _stream()))
         return g, loss
+
+    def gradients_noalloc(self, X, y, grad, loss):
+        """pd_closure_gradients_noalloc into the caller's grad [N_PARAMS] and loss [1]
+        (FP32 device tensors); at most NOALLOC_MAX_ROWS rows."""
+        n = X.shape[0]
+        _check(self.L.pd_closure_gradients_noalloc(self.h, self._X(X, n), self._y(y, n), n,
+                                                   self._y(grad, N_PARAMS, "grad"),
+                                                   self._y(loss, 1, "loss"), _stream()))
+        return grad, loss
 
     def train(self, X, y, batch=4096, epochs=1, lr=1e-3, seed=0):
         losses = self._np.zeros(max(epochs, 1), dtype=self._np.float32)

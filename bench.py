@@ -45,9 +45,8 @@ def workload(name):
                          "source (1 + sin 4 pi t) g")
 
 
-BURST_SOURCES = ["pd_burst.inc", "pd_internal.h", "pd_burst_x_f64.hip", "pd_burst_x_f32.hip",
-                 "pd_burst_lds_f64.hip", "pd_burst_lds_f32.hip", "pd_burst_h_f64.hip",
-                 "pd_burst_h_f32.hip"]
+BURST_SOURCES = ["pd_burst.inc", "pd_internal.h"] + [
+    f"pd_burst_{fam}_{prec}.hip" for fam in ("x", "lds", "h") for prec in ("f64", "f32")]
 
 
 FD_SOURCES = ["pd_fd.hip", "pd_internal.h"]
@@ -128,6 +127,147 @@ def pmc_summary(fetch_csv, write_csv, kernel_prefix, calib_mib, out, command, wo
         fh.write(f"hbm_bytes_per_launch: {total:.6e}\n")
         fh.write(f"source_sha256: {burst_source_hash(files)}\n")
     print(open(out).read())
+
+
+# rocprofv3 --pmc passes for the utilisation figures (each fits one pass: at most 8 SQ and
+# 2 GRBM counters, derived metrics counted by their inputs).
+COUNTER_PASSES = {
+    "valu": ["SQ_INSTS_VALU", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+             "SQ_INSTS_VALU_MUL_F64", "VALUBusy", "VALUUtilization"],
+    "lds": ["SQ_INSTS_LDS", "SQ_WAIT_INST_LDS", "LdsUtil", "LdsBankConflict", "MfmaUtil",
+            "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_VALU_FMA_F32"],
+}
+CUS, CLOCK = 256, 2.4e9  # MI355X compute units and peak engine clock
+# One wave64 VALU instruction occupies a 16-lane SIMD for 4 clocks and a CU has 4 SIMDs:
+# the chip issues at most CUS * CLOCK wave instructions per second.
+VALU_ISSUE_PEAK = CUS * CLOCK
+PEAK_MFMA_BF16 = 2.5e15
+
+
+def calibration_copy(mib):
+    """A plain streaming kernel of known traffic for scaling HBM byte counters: torch's
+    vectorized elementwise multiply by one reading MIB MiB and writing MIB MiB, twice."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def stats_summary(csv_path, out, title, command, top=14):
+    """A rocprofv3 --stats kernel table (kernel_stats.csv) as a short text summary."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    with open(out, "w") as fh:
+        for line in title.strip().splitlines():
+            fh.write(f"# {line}\n")
+        fh.write(f"# command:\n#   {command}\n")
+        fh.write(f"{'kernel':<66} {'calls':>6} {'avg_us':>12} {'min_us':>12} {'max_us':>12} "
+                 f"{'total_ms':>12} {'pct':>7}\n")
+        for r in rows[:top]:
+            fh.write(f"{r['Name'][:66]:<66} {int(r['Calls']):>6} "
+                     f"{float(r['AverageNs']) / 1e3:>12.2f} {float(r['MinNs']) / 1e3:>12.2f} "
+                     f"{float(r['MaxNs']) / 1e3:>12.2f} {float(r['TotalDurationNs']) / 1e6:>12.3f} "
+                     f"{float(r['Percentage']):>7.2f}\n")
+    print(open(out).read())
+
+
+def counter_file(kernel, workload, precision):
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_counters.txt")
+
+
+def counter_summary(csvs, kernel_prefix, last, out, command, workload, precision, shape,
+                    files=None):
+    """Per-dispatch averages of rocprofv3 --pmc counters for one kernel (the last `last`
+    dispatches of it in each file when last > 0), with the per-launch counts the bench
+    lines turn into rates: VALU wave instructions, FP64 flops issued (64 lanes x (add + mul
+    + 2 fma) instructions), bfloat16 MFMA flops (512 per MOPS unit), LDS instructions."""
+    import csv
+    vals, durs, counts = {}, [], {}
+    for path in csvs:
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if kernel_prefix not in r["Kernel_Name"]:
+                continue
+            d = int(r["Dispatch_Id"])
+            e = per.setdefault(d, {"dur": float(r["End_Timestamp"]) - float(r["Start_Timestamp"])})
+            e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        ids = sorted(per)
+        if last > 0:
+            ids = ids[-last:]
+        if not ids:
+            raise SystemExit(f"{path}: no dispatches of {kernel_prefix}")
+        for d in ids:
+            durs.append(per[d]["dur"])
+            for k, v in per[d].items():
+                if k != "dur":
+                    vals.setdefault(k, []).append(v)
+        counts[f"pass {len(counts) + 1}"] = len(ids)
+    avg = {k: sum(v) / len(v) for k, v in vals.items()}
+    g = lambda k: avg.get(k, 0.0)
+    derived = {
+        "valu_insts_per_launch": g("SQ_INSTS_VALU"),
+        "fp64_flops_per_launch": 64.0 * (g("SQ_INSTS_VALU_ADD_F64") + g("SQ_INSTS_VALU_MUL_F64")
+                                         + 2.0 * g("SQ_INSTS_VALU_FMA_F64")),
+        "fp32_fma_insts_per_launch": g("SQ_INSTS_VALU_FMA_F32"),
+        "mfma_bf16_flops_per_launch": 512.0 * g("SQ_INSTS_VALU_MFMA_MOPS_BF16"),
+        "lds_insts_per_launch": g("SQ_INSTS_LDS"),
+        "pmc_run_launch_us": sum(durs) / len(durs) / 1e3,
+    }
+    with open(out, "w") as fh:
+        fh.write(f"# rocprofv3 counters of {kernel_prefix} ({workload}, {precision}), averaged per "
+                 "dispatch" + (f" over the last {last} dispatches of each pass" if last else "")
+                 + "\n")
+        fh.write("# commands (one pass per counter set; <set> is each key of COUNTER_PASSES in "
+                 f"bench.py):\n#   {command}\n")
+        fh.write("# VALUBusy, VALUUtilization, LdsUtil, LdsBankConflict, MfmaUtil: rocprofv3's "
+                 "derived metrics (percent; LdsBankConflict in conflicts per access)\n")
+        fh.write(f"kernel: {kernel_prefix}\nworkload: {workload}\nprecision: {precision}\n"
+                 f"shape: {shape}\n")
+        fh.write("dispatches: " + ", ".join(f"{v} ({k})" for k, v in counts.items()) + "\n")
+        for k in sorted(avg):
+            fh.write(f"{k}: {avg[k]:.6e}\n")
+        for k, v in derived.items():
+            fh.write(f"{k}: {v:.6e}\n")
+        fh.write(f"source_sha256: {burst_source_hash(files)}\n")
+    print(open(out).read())
+
+
+def read_counters(kernel, workload, precision, shape, kern_s, files=None):
+    """Utilisation of one launch of `kern_s` seconds (the bench's own live timing) from the
+    committed counter summary: VALU issue-slot fraction, FP64 and bfloat16 MFMA rates
+    against their peaks, and rocprofv3's busy/utilisation metrics.  None when there is no
+    summary for this kernel, workload and launch shape, or the kernel changed since."""
+    path = counter_file(kernel, workload, precision)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != burst_source_hash(files) or kv.get("shape") != shape:
+        return None
+    f = lambda k: float(kv[k]) if k in kv else None
+    out = {"source": os.path.relpath(path, ROOT),
+           "valu_insts_per_launch": f("valu_insts_per_launch"),
+           "valu_issue_frac": f("valu_insts_per_launch") / kern_s / VALU_ISSUE_PEAK,
+           "fp64_issued_tflops": f("fp64_flops_per_launch") / kern_s / 1e12,
+           "fp64_issued_frac": f("fp64_flops_per_launch") / kern_s / PEAK["f64"],
+           "lds_insts_per_launch": f("lds_insts_per_launch"),
+           "pmc_run_launch_us": f("pmc_run_launch_us")}
+    if f("mfma_bf16_flops_per_launch"):
+        out["mfma_bf16_tflops"] = f("mfma_bf16_flops_per_launch") / kern_s / 1e12
+        out["mfma_bf16_frac"] = f("mfma_bf16_flops_per_launch") / kern_s / PEAK_MFMA_BF16
+    for k in ("VALUBusy", "VALUUtilization", "LdsUtil", "LdsBankConflict", "MfmaUtil"):
+        if k in kv:
+            out[k] = float(kv[k])
+    return out
 
 
 def cpu_baseline(prob, budget_s, steps_cap):
@@ -303,7 +443,9 @@ def batch_line(grids, B, tuned_ms, el, ev_s, args, untuned_items=None):
             "kernel": "k_batch (persistent, one batch macro step per launch)",
             "kernel_ms": kern_s * 1e3, "flops_per_update": 20,
             "issued_flops_per_update": 12,
-            "issued_frac": 12 * per_step / kern_s / peak}
+            "issued_frac": 12 * per_step / kern_s / peak,
+            "counters": read_counters("k_batch", "config4", "f64", "tuned", kern_s,
+                                      BATCH_SOURCES)}
     return per_step, cfg, roof
 
 
@@ -320,6 +462,8 @@ def bench_batch(args):
                                                log)
         log(f"batch of {len(grids)} ready in {time.perf_counter() - t0:.1f} s")
         el, ev_s = time_batch(B, grids, args.warmup, args.steps, stream)
+        if args.calibrate_copy:
+            calibration_copy(args.calibrate_copy)
     per_step, cfg, roof = batch_line(grids, B, tuned_ms, el, ev_s, args)
     out = {
         "metric": "patch-point updates/s (and macro steps/s) of the batched plain scheme",
@@ -455,6 +599,8 @@ def bench_headline(args, workload_name="config4+config5"):
         if args.horizon_steps > 0:
             surrogate["rel_l2_vs_plain_long_horizon"] = closure_horizon(args, C, threshold,
                                                                         log)
+        if args.calibrate_copy:
+            calibration_copy(args.calibrate_copy)
     per_step, cfg, roof = batch_line(grids, B, tuned_ms, el, ev_s, args)
     out = {
         "metric": "patch-point updates/s + macro steps/s at fixed L2 err; surrogate vs "
@@ -501,6 +647,8 @@ def bench_refresh(args):
         g = pd.Grid(prob)
         U = g.initial()
         V = g.new_U()
+        # the sub-bursts run on the grid's launch shape (split mode), tuned on the fused step
+        tuned_ms = None if args.no_autotune else g.autotune(U, reps=5)
         for s in range(args.warmup):
             g.macro_step_refresh(U, t["t0"] + s * t["dt_macro"], Q, out=V)
             U, V = V, U
@@ -553,10 +701,15 @@ def bench_refresh(args):
         "config": {"workload": f"refresh: config-2 problem (65x65 macro nodes, 17x17 micro "
                                f"points per patch, n_t = {t['n_t']}) with the edge data "
                                f"refreshed {Q - 1} times per burst ({Q} sub-bursts)",
-                   "n_refresh": Q, "updates_per_step": per_step},
+                   "n_refresh": Q, "updates_per_step": per_step,
+                   "launch": {"exchange": {1: "lds", 2: "in-wave", 3: "hybrid"}[info.exchange],
+                              "cols_per_lane": info.cols_per_lane,
+                              "rows_per_lane": info.rows_per_lane,
+                              "patches_per_block": info.patches_per_block,
+                              "block_threads": info.block_threads, "tuned_ms": tuned_ms}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["f64"] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK["f64"], "traffic": None,
-                     "kernel": "k_burst (LDS exchange, split mode: one sub-burst)",
+                     "kernel": KERNEL_NAME[info.exchange] + " (split mode: one sub-burst)",
                      "kernel_ms": kern_s * 1e3, "flops_per_update": 20},
         "frozen_edge_fused_ms_per_step": t_fused * 1e3,
     }
@@ -959,6 +1112,18 @@ def main():
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic summary of the burst kernel from two "
                          "rocprofv3 --pmc counter CSVs (no GPU needed) and exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
+                    help="write the utilisation summary of one kernel (--counter-kernel) from "
+                         "rocprofv3 --pmc counter CSVs of the COUNTER_PASSES sets (no GPU "
+                         "needed) and exit")
+    ap.add_argument("--stats-summary", nargs=2, metavar=("KERNEL_STATS_CSV", "OUT"),
+                    help="write a rocprofv3 --stats kernel table as a text summary (with "
+                         "--stats-title and --pmc-command) and exit")
+    ap.add_argument("--stats-title", default="")
+    ap.add_argument("--counter-kernel", default="",
+                    help="kernel name as in profiles/ (k_burst_x, k_batch, k_closure_step, ...)")
+    ap.add_argument("--counter-last", type=int, default=0,
+                    help="summarise only the last N dispatches of the kernel in each CSV")
     ap.add_argument("--pmc-shape", default="", help="launch shape the counters were taken at")
     ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
@@ -970,6 +1135,19 @@ def main():
                        "config2": 32, "config3": 32}.get(args.workload, 4)
     if args.warmup < 0 or args.steps < 1:
         ap.error("--steps must be >= 1 and --warmup >= 0")
+    if args.stats_summary:
+        stats_summary(args.stats_summary[0], args.stats_summary[1], args.stats_title,
+                      args.pmc_command)
+        return
+    if args.counter_summary:
+        kern = args.counter_kernel
+        files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
+                 "k_burst_hu": HU_SOURCES, "k_fd_step": FD_SOURCES}.get(kern)
+        counter_summary(args.counter_summary, kern + ("<" if kern.startswith("k_burst") or
+                                                      kern == "k_batch" else ""),
+                        args.counter_last, counter_file(kern, args.workload, args.precision),
+                        args.pmc_command, args.workload, args.precision, args.pmc_shape, files)
+        return
     if args.pmc_summary:
         if args.workload == "full-domain":
             pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_fd_step",
@@ -1117,7 +1295,9 @@ def main():
                      "kernel_ms": kern_s * 1e3,
                      "flops_per_update": flops_per_update,
                      "issued_flops_per_update": issued_flops_per_update,
-                     "issued_frac": issued_flops_per_update * per_step / kern_s / peak},
+                     "issued_frac": issued_flops_per_update * per_step / kern_s / peak,
+                     "counters": read_counters(KERNEL_NAME[info.exchange], args.workload,
+                                               args.precision, shape, kern_s)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, steps_cap=1000)

@@ -1,11 +1,11 @@
-// F64 burst kernels with the hybrid neighbour exchange (DPP inside each wave, band edges
-// through LDS).
+// F64 burst kernels with the hybrid neighbour exchange (DPP inside each wave, band
+// edges through LDS): fused macro step (Sec. 3.3 steps (i)-(vi) in one launch).
 #include "pd_internal.h"
 #include "pd_burst.inc"
 
 namespace pdk {
-hipError_t launch_burst_h_f64(int R, int C, int mode, const BurstArgs& a, int blocks,
-                            int threads, size_t lds, hipStream_t s) {
-  return launch_family<double, XCH_HYBRID>(R, C, mode, a, blocks, threads, lds, s);
+hipError_t launch_burst_h_f64(int R, int C, const BurstArgs& a, int blocks,
+                              int threads, size_t lds, hipStream_t s) {
+  return launch_family<double, XCH_HYBRID, MODE_FUSED>(R, C, a, blocks, threads, lds, s);
 }
 }  // namespace pdk

@@ -1,4 +1,5 @@
-// F64 burst kernels with the neighbour exchange through LDS.
+// F64 burst kernels with the neighbour exchange through LDS: fused macro step (Sec. 3.3
+// steps (i)-(vi) in one launch).
 #include "pd_internal.h"
 #include "pd_burst.inc"
 
@@ -12,8 +13,8 @@ hipError_t launch_time_table(const SrcInfo& src, double t_n, double dt, int n_t,
   return hipGetLastError();
 }
 
-hipError_t launch_burst_lds_f64(int R, int C, int mode, const BurstArgs& a, int blocks,
-                           int threads, size_t lds, hipStream_t s) {
-  return launch_family<double, XCH_LDS>(R, C, mode, a, blocks, threads, lds, s);
+hipError_t launch_burst_lds_f64(int R, int C, const BurstArgs& a, int blocks,
+                                int threads, size_t lds, hipStream_t s) {
+  return launch_family<double, XCH_LDS, MODE_FUSED>(R, C, a, blocks, threads, lds, s);
 }
 }  // namespace pdk

@@ -1,10 +1,11 @@
-// F64 burst kernels with the neighbour exchange inside one wave (DPP / ds_bpermute).
+// F64 burst kernels with the neighbour exchange inside one wave (DPP / ds_bpermute): fused
+// macro step (Sec. 3.3 steps (i)-(vi) in one launch).
 #include "pd_internal.h"
 #include "pd_burst.inc"
 
 namespace pdk {
-hipError_t launch_burst_x_f64(int R, int C, int mode, const BurstArgs& a, int blocks,
-                           int threads, size_t lds, hipStream_t s) {
-  return launch_family<double, XCH_LANES>(R, C, mode, a, blocks, threads, lds, s);
+hipError_t launch_burst_x_f64(int R, int C, const BurstArgs& a, int blocks,
+                              int threads, size_t lds, hipStream_t s) {
+  return launch_family<double, XCH_LANES, MODE_FUSED>(R, C, a, blocks, threads, lds, s);
 }
 }  // namespace pdk

@@ -1,0 +1,11 @@
+// F32 burst kernels with the neighbour exchange inside one wave (DPP / ds_bpermute):
+// split-mode burst (step (iii) on caller-owned patch states).
+#include "pd_internal.h"
+#include "pd_burst.inc"
+
+namespace pdk {
+hipError_t launch_burst_xs_f32(int R, int C, const BurstArgs& a, int blocks,
+                               int threads, size_t lds, hipStream_t s) {
+  return launch_family<float, XCH_LANES, MODE_SPLIT>(R, C, a, blocks, threads, lds, s);
+}
+}  // namespace pdk

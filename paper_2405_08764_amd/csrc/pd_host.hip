@@ -19,27 +19,38 @@
 
 namespace pdk {
 #define PD_DECL(tag)                                                                      \
-  hipError_t launch_burst_##tag(int R, int C, int mode, const BurstArgs& a, int blocks,   \
-                                int threads, size_t lds, hipStream_t s);
+  hipError_t launch_burst_##tag(int R, int C, const BurstArgs& a, int blocks, int threads, \
+                                size_t lds, hipStream_t s);
 PD_DECL(lds_f64)
 PD_DECL(lds_f32)
 PD_DECL(x_f64)
 PD_DECL(x_f32)
 PD_DECL(h_f64)
 PD_DECL(h_f32)
+PD_DECL(ldss_f64)
+PD_DECL(ldss_f32)
+PD_DECL(xs_f64)
+PD_DECL(xs_f32)
+PD_DECL(hs_f64)
+PD_DECL(hs_f32)
 #undef PD_DECL
 
+// The burst kernel of one exchange family, precision and mode (fused macro step or
+// split-mode burst on caller-owned patch states); every family runs both modes.
 hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const BurstArgs& a,
                         int blocks, int threads, size_t lds, hipStream_t s) {
-  if (mode == MODE_SPLIT) xch = XCH_LDS;  // the in-wave kernels are fused-only
+  const bool f32 = precision == PD_F32, split = mode == MODE_SPLIT;
+  decltype(&launch_burst_lds_f64) fn;
   if (xch == XCH_LANES)
-    return precision == PD_F32 ? launch_burst_x_f32(R, C, mode, a, blocks, threads, lds, s)
-                               : launch_burst_x_f64(R, C, mode, a, blocks, threads, lds, s);
-  if (xch == XCH_HYBRID)
-    return precision == PD_F32 ? launch_burst_h_f32(R, C, mode, a, blocks, threads, lds, s)
-                               : launch_burst_h_f64(R, C, mode, a, blocks, threads, lds, s);
-  return precision == PD_F32 ? launch_burst_lds_f32(R, C, mode, a, blocks, threads, lds, s)
-                             : launch_burst_lds_f64(R, C, mode, a, blocks, threads, lds, s);
+    fn = split ? (f32 ? launch_burst_xs_f32 : launch_burst_xs_f64)
+               : (f32 ? launch_burst_x_f32 : launch_burst_x_f64);
+  else if (xch == XCH_HYBRID)
+    fn = split ? (f32 ? launch_burst_hs_f32 : launch_burst_hs_f64)
+               : (f32 ? launch_burst_h_f32 : launch_burst_h_f64);
+  else
+    fn = split ? (f32 ? launch_burst_ldss_f32 : launch_burst_ldss_f64)
+               : (f32 ? launch_burst_lds_f32 : launch_burst_lds_f64);
+  return fn(R, C, a, blocks, threads, lds, s);
 }
 
 bool burst_shape_supported(int R, int C) {
@@ -128,11 +139,8 @@ struct pd_grid_s {
   double lim_micro = 0.0, lim_macro = 0.0;
   // options
   int allow_unstable = 0, opt_R = 0, opt_C = 0, opt_ppb = 0, opt_threads = 0, opt_xch = 0;
-  // launch shape
+  // launch shape of the burst, fused and split mode alike
   int R = 0, C = 0, xch = 0, ppb = 0, threads = 0, blocks = 0;
-  // split-mode launch shape (always the LDS-exchange kernel)
-  int sR = 0, sC = 0, sppb = 0, sthreads = 0, sblocks = 0;
-  size_t slds = 0;
   size_t lds = 0;
   // graph replay of pd_solve
   hipStream_t cap = nullptr;
@@ -182,19 +190,21 @@ void drop_graph(pd_grid g) {
 // neighbour exchange.  Candidates are ranked by the useful fraction of the lane slots
 // (idle lanes and padding points are wasted VALU issue), weighted 1.5x for the in-wave
 // exchange (no LDS traffic and no barrier in the nano-step loop; measured about that much
-// faster per lane slot); on ties, wider lane blocks (fewer exchanged values per point),
-// more rows, then smaller blocks.  pd_autotune replaces this guess by measurement.
+// faster per lane slot) and 1.2x for the hybrid one (measured on 17 x 17 patches: slower
+// per nano step than the in-wave kernel and close to the LDS one); on ties, wider lane
+// blocks (fewer exchanged values per point), more rows, then smaller blocks.  The same
+// shape serves the fused step and the split-mode burst.  pd_autotune replaces this guess
+// by measurement.
 struct Shape {
   int R, C, xch, ppb, threads;
   double score;
 };
 
-bool next_shape(pd_grid g, int xch_only, bool split, std::vector<Shape>& out) {
+bool next_shape(pd_grid g, int xch_only, std::vector<Shape>& out) {
   const int mx = g->g.m_xi, me = g->g.m_eta;
   const int candR[] = {2, 3, 4, 5, 6, 7, 8, 9, 11};
   out.clear();
   for (int xch = XCH_LDS; xch <= XCH_HYBRID; ++xch) {
-    if (split && xch != XCH_LDS) continue;
     if (xch_only && xch != xch_only) continue;
     for (int C = 1; C <= 4; ++C) {
       if (g->opt_C && C != g->opt_C) continue;
@@ -224,7 +234,7 @@ bool next_shape(pd_grid g, int xch_only, bool split, std::vector<Shape>& out) {
           // the prologue stages the stencil tables at TAB_STAGE values per team thread
           if (tab_off(mx, me).size > TAB_STAGE * (xch == XCH_LANES ? 64 : threads)) continue;
           const double eff = (double)ppb * mx * me / ((double)threads * R * C);
-          const double w = xch == XCH_LANES ? 1.5 : (xch == XCH_HYBRID ? 1.4 : 1.0);
+          const double w = xch == XCH_LANES ? 1.5 : (xch == XCH_HYBRID ? 1.2 : 1.0);
           const double score = eff * w + 1e-3 * (C - 1) + 1e-4 * R - 1e-5 * threads;
           out.push_back({R, C, xch, ppb, threads, score});
         }
@@ -260,24 +270,11 @@ std::map<TuneKey, std::pair<Shape, double>> g_tune;
 void choose_shape(pd_grid g) {
   std::vector<Shape> c;
   g->R = 0;
-  g->sR = 0;
-  if (next_shape(g, g->opt_xch, false, c)) {
+  if (next_shape(g, g->opt_xch, c)) {
     const Shape* b = &c[0];
     for (const Shape& x : c)
       if (x.score > b->score) b = &x;
     apply_shape(g, *b);
-  }
-  if (next_shape(g, XCH_LDS, true, c)) {
-    const Shape* b = &c[0];
-    for (const Shape& x : c)
-      if (x.score > b->score) b = &x;
-    g->sR = b->R;
-    g->sC = b->C;
-    g->sppb = b->ppb;
-    g->sthreads = b->threads;
-    g->sblocks = (g->g.P + b->ppb - 1) / b->ppb;
-    g->slds = burst_lds_bytes(g->d.precision, b->R, b->C, XCH_LDS, b->threads, b->ppb,
-                              g->g.m_xi, g->g.m_eta, g->src.ns);
   }
 }
 
@@ -317,7 +314,7 @@ pd_status need_coeffs(pd_grid g) {
   pd_status s = need_ws(g);
   if (s) return s;
   if (!g->coeffs_set) return fail(PD_ESTATE, "coefficients not set");
-  if (!g->R || !g->sR) return fail(PD_EINVAL, "no supported burst launch shape for this patch size");
+  if (!g->R) return fail(PD_EINVAL, "no supported burst launch shape for this patch size");
   return PD_OK;
 }
 
@@ -649,10 +646,9 @@ pd_status pd_micro_burst(pd_grid g, double* state, const double* edge, double t_
   BurstArgs a = base_args(g, t_n, dt, n_t);
   a.state = state;
   a.edge = edge;
-  a.ppb = g->sppb;
   HIPCHK(ensure_time_table(g, t_n, dt, n_t, static_cast<hipStream_t>(stream)));
-  HIPCHK(launch_burst(g->d.precision, g->sR, g->sC, XCH_LDS, MODE_SPLIT, a, g->sblocks,
-                      g->sthreads, g->slds, static_cast<hipStream_t>(stream)));
+  HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_SPLIT, a, g->blocks,
+                      g->threads, g->lds, static_cast<hipStream_t>(stream)));
   return PD_OK;
 }
 
@@ -906,7 +902,7 @@ pd_status pd_autotune(pd_grid g, const double* U, double t_n, double dt_macro, d
     }
   }
   std::vector<Shape> cand;
-  if (!next_shape(g, g->opt_xch, false, cand)) return fail(PD_EINVAL, "no launch shape to tune");
+  if (!next_shape(g, g->opt_xch, cand)) return fail(PD_EINVAL, "no launch shape to tune");
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

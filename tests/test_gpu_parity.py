@@ -124,14 +124,21 @@ def test_lift_bc_and_restrict_match_oracle(pd, oracle_mod, problems, case):
     np.testing.assert_allclose(Ub, o.restrict(u_o), rtol=1e-14, atol=1e-15)
 
 
+@pytest.mark.parametrize("xch", [0, 1, 2, 3])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("case", CASE_NAMES)
-def test_burst_matches_oracle(pd, oracle_mod, problems, case, precision):
-    """Step (iii) on its own, from the oracle's lifted field and edge data: the change
-    u(tau) - u(0) agrees."""
+def test_burst_matches_oracle(pd, oracle_mod, problems, case, precision, xch):
+    """Step (iii) on its own, from the oracle's lifted field and edge data, on the
+    automatic launch shape (xch 0) and on each neighbour-exchange family (LDS, in-wave,
+    hybrid) where the patch fits it: the change u(tau) - u(0) agrees."""
     prob = problems[case]
-    say("burst", case, precision)
+    say("burst", case, precision, "exchange", xch)
     g = pd.Grid(prob, precision=precision)
+    if xch:
+        try:
+            g.set_option(pd.OPT_EXCHANGE, xch)
+        except pd.PdError:
+            pytest.skip(f"no launch shape with exchange {xch} for this patch size")
     o = oracle_mod.Oracle(prob, extended=True)
     U0 = o.initial()
     u0, e0 = o.lift(U0), o.edge(U0)
@@ -277,6 +284,41 @@ def test_bitwise_determinism_across_runs_and_launch_shapes(pd, problems):
                     seen.add(key)
                     out = g.solve().cpu().numpy()
                     assert out.tobytes() == ref.tobytes(), key
+    assert {k[0] for k in seen} == {1, 2, 3}, seen
+
+
+def test_split_burst_bitwise_across_launch_shapes(pd, problems):
+    """The split-mode burst (caller-owned patch states) gives the same bits on every
+    supported launch shape of every exchange family, as the fused step does."""
+    prob = problems["config2_17x17"]
+    g = pd.Grid(prob)
+    t = prob["time"]
+    U = g.initial()
+    st0, ed = g.lift_bc(U)
+    st = st0.clone()
+    g.micro_burst(st, ed, 0.0, t["dt_micro"], t["n_t"])
+    ref = st.cpu().numpy()
+    seen = set()
+    for xch in (1, 2, 3):
+        for C in (1, 2, 3, 4):
+            for R in (2, 3, 4, 5, 6, 7, 8, 9, 11):
+                for ppb in (1, 2, 0):
+                    try:
+                        g.set_option(pd.OPT_EXCHANGE, xch)
+                        g.set_option(pd.OPT_COLS_PER_LANE, C)
+                        g.set_option(pd.OPT_ROWS_PER_LANE, R)
+                        g.set_option(pd.OPT_PATCHES_PER_BLOCK, ppb)
+                    except pd.PdError:
+                        continue
+                    I = g.query()
+                    key = (I.exchange, I.cols_per_lane, I.rows_per_lane, I.patches_per_block)
+                    if (I.exchange, I.cols_per_lane, I.rows_per_lane) != (xch, C, R) or key in seen:
+                        continue
+                    seen.add(key)
+                    st = st0.clone()
+                    g.micro_burst(st, ed, 0.0, t["dt_micro"], t["n_t"])
+                    assert st.cpu().numpy().tobytes() == ref.tobytes(), key
+    say("split shapes", len(seen))
     assert {k[0] for k in seen} == {1, 2, 3}, seen
 
 

@@ -33,8 +33,10 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("xch", [0, 1, 2, 3])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_refresh_matches_oracle(pd, oracle_mod, name):
+def test_refresh_matches_oracle(pd, oracle_mod, name, xch):
+    """Every sub-burst on the automatic launch shape (xch 0) or on one exchange family."""
     make, Q, steps = CASES[name]
     prob = make()
     g = pd.Grid(prob)
@@ -44,7 +46,12 @@ def test_refresh_matches_oracle(pd, oracle_mod, name):
         prob = W.fit_time(prob, info.dt_macro_limit, info.dt_micro_limit, steps)
         g = pd.Grid(prob)
         t = prob["time"]
-    say(name, "Q", Q, "n_t", t["n_t"], "steps", steps)
+    if xch:
+        try:
+            g.set_option(pd.OPT_EXCHANGE, xch)
+        except pd.PdError:
+            pytest.skip(f"no launch shape with exchange {xch} for this patch size")
+    say(name, "Q", Q, "n_t", t["n_t"], "steps", steps, "exchange", g.query().exchange)
     o = oracle_mod.Oracle(prob)
     U = g.initial()
     Uo = U.cpu().numpy().copy()

@@ -35,6 +35,15 @@ CASES = {
     "ragged_13x7": (lambda: W.problem(W.grid("sine", 5, 6, 13, 7, gparam=0.2, conv="central"),
                                       W.config1()["fields"], W.config1()["bc"],
                                       W.config1()["src"], W.timing(1e-3, 1, 2)), 25.0, 3),
+    # lines of at most 12 points run on the register-line kernel: uneven patches both ways,
+    # upwind and central, with and without a time-dependent source
+    "ragged_11x7": (lambda: W.problem(W.grid("sine", 5, 6, 11, 7, gparam=0.2, conv="upwind"),
+                                      W.config1()["fields"], W.config1()["bc"],
+                                      W.config1()["src"], W.timing(1e-3, 1, 2)), 25.0, 3),
+    "ragged_5x12": (lambda: W.problem(W.grid("tanh", 6, 5, 5, 12, gparam=1.5, conv="central"),
+                                      W.config1()["fields"], W.config1()["bc"],
+                                      W.config1()["src"], W.timing(1e-3, 1, 2)), 25.0, 2),
+    "sec411_m3": (lambda: W.paper_cdr(1, lam=0.1, n=6, m=3), None, 2),
 }
 
 

@@ -51,6 +51,7 @@ BURST_SOURCES = ["pd_burst.inc", "pd_internal.h"] + [
 
 FD_SOURCES = ["pd_fd.hip", "pd_internal.h"]
 HU_SOURCES = ["pd_upwind.hip", "pd_internal.h"]
+ADI_SOURCES = ["pd_adi.hip", "pd_internal.h"]
 
 
 def burst_source_hash(files=None):
@@ -888,7 +889,8 @@ def bench_upwind(args):
                 torch.mul(src, 1.0, out=dst)
             torch.cuda.synchronize()
             del src, dst
-    traffic = read_traffic("k_burst_hu", "upwind", "f64", "hu", HU_SOURCES)
+    # config 2's 17 x 17 patches fit one wave: the in-wave kernel runs
+    traffic = read_traffic("k_burst_hux", "upwind", "f64", "hux", HU_SOURCES)
     pts = info.n_points
     n_src = len(prob["src"])
     # per point and nano step: the folded 9-point cross on the increment (a multiply, eight
@@ -912,7 +914,8 @@ def bench_upwind(args):
                      "frac": flops_per_update * pts * n_t / kern_s / PEAK["f64"],
                      "traffic": traffic, "algorithmic_bytes": alg_bytes,
                      "hbm_frac": alg_bytes / kern_s / 8e12,
-                     "kernel": f"k_burst_hu (one {form} burst)", "kernel_ms": kern_s * 1e3,
+                     "kernel": f"k_burst_hux (in-wave, one {form} burst)",
+                     "kernel_ms": kern_s * 1e3,
                      "kernel_ms_by_form": {k: v * 1e3 for k, v in kern.items()},
                      "flops_per_update": flops_per_update},
     }
@@ -1142,7 +1145,8 @@ def main():
     if args.counter_summary:
         kern = args.counter_kernel
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
-                 "k_burst_hu": HU_SOURCES, "k_fd_step": FD_SOURCES}.get(kern)
+                 "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
+                 "k_fd_step": FD_SOURCES}.get(kern)
         counter_summary(args.counter_summary, kern + ("<" if kern.startswith("k_burst") or
                                                       kern == "k_batch" else ""),
                         args.counter_last, counter_file(kern, args.workload, args.precision),
@@ -1156,10 +1160,10 @@ def main():
                         args.workload, "f64", "fd", FD_SOURCES)
             return
         if args.workload == "upwind":
-            pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_burst_hu",
+            pmc_summary(args.pmc_summary[0], args.pmc_summary[1], "k_burst_hux",
                         args.calibrate_copy or 256,
-                        traffic_file("k_burst_hu", args.workload, "f64"), args.pmc_command,
-                        args.workload, "f64", "hu", HU_SOURCES)
+                        traffic_file("k_burst_hux", args.workload, "f64"), args.pmc_command,
+                        args.workload, "f64", "hux", HU_SOURCES)
             return
         kernel = KERNEL_NAME[int(args.pmc_shape.split(",")[0])]
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], kernel + "<",

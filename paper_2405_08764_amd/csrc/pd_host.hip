@@ -692,7 +692,7 @@ pd_status pd_micro_burst_upwind(pd_grid g, double* state, const double* edge, do
   HIPCHK(hipSetDevice(g->d.device));
   HIPCHK(launch_burst_hu(g->g, g->src, g->coef(), (long long)g->g.P * g->g.m_xi * g->g.m_eta,
                          state, edge, t_n, dt, n_t, points, r, g->flag(),
-                         static_cast<hipStream_t>(stream)));
+                         g->opt_xch == XCH_LDS, static_cast<hipStream_t>(stream)));
   return PD_OK;
 }
 

@@ -159,10 +159,11 @@ hipError_t launch_burst_adi(const Geo& g, const SrcInfo& src, const double* coef
 // 1024 micro points per block, the patches' ghost-framed tiles within HU_LDS_MAX.
 constexpr size_t HU_LDS_MAX = 65536;
 void hu_shape(int mx, int me, int& ppb, size_t& lds);
+// lds_only: the LDS-tile kernel even where a patch fits the in-wave kernel's lane blocks.
 hipError_t launch_burst_hu(const Geo& g, const SrcInfo& src, const double* coef,
                            long long plane, double* state, const double* edge, double t_n,
                            double dt, int n_t, int points, double r, int* flag,
-                           hipStream_t s);
+                           bool lds_only, hipStream_t s);
 
 // ---------------------------------------------------------------- full-domain lattice
 // The explicit comparator on one lattice over the whole box: a Geo whose n_xi x n_eta

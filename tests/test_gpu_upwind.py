@@ -49,8 +49,11 @@ CASES = {
 FORMS = [(2, 0.0), (3, 0.0), (4, 0.5), (4, 1.0 / 3.0)]
 
 
-def burst_case(pd, oracle_mod, prob, points, r, n_t, factor, seed):
+def burst_case(pd, oracle_mod, prob, points, r, n_t, factor, seed, lds=False):
+    """lds: the LDS-tile kernel even where the patch fits the in-wave kernel."""
     g = pd.Grid(prob)
+    if lds:
+        g.set_option(pd.OPT_EXCHANGE, 1)
     o = oracle_mod.Oracle(prob)
     dt = factor * g.query().dt_micro_limit
     U = g.initial() + 0.1 * torch.randn(g.new_U().shape, dtype=torch.float64,
@@ -66,28 +69,52 @@ def burst_case(pd, oracle_mod, prob, points, r, n_t, factor, seed):
     return float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref))))
 
 
+@pytest.mark.parametrize("lds", [False, True], ids=["auto", "lds"])
 @pytest.mark.parametrize("form", FORMS, ids=lambda f: f"p{f[0]}r{f[1]:.2f}")
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_upwind_burst_matches_oracle(pd, oracle_mod, name, form):
+def test_upwind_burst_matches_oracle(pd, oracle_mod, name, form, lds):
+    """Both kernels: the in-wave one wherever the patch fits a wave (all but m = 32 here)
+    and the LDS-tile one."""
     points, r = form
-    err = burst_case(pd, oracle_mod, CASES[name](), points, r, 5, 0.4, 7)
-    say(name, points, r, "max rel err", err)
+    err = burst_case(pd, oracle_mod, CASES[name](), points, r, 5, 0.4, 7, lds)
+    say(name, points, r, "lds" if lds else "auto", "max rel err", err)
     assert err <= TOL, err
 
 
-def test_long_burst_matches_oracle(pd, oracle_mod):
-    """Many nano steps (the ping-pong tiles and ghost layers over a long run)."""
-    err = burst_case(pd, oracle_mod, W.config2(n=6, m=17), 3, 0.0, 61, 0.3, 11)
+@pytest.mark.parametrize("lds", [False, True], ids=["auto", "lds"])
+def test_long_burst_matches_oracle(pd, oracle_mod, lds):
+    """Many nano steps (the ping-pong state and ghost layers over a long run)."""
+    err = burst_case(pd, oracle_mod, W.config2(n=6, m=17), 3, 0.0, 61, 0.3, 11, lds)
     say("long burst max rel err", err)
     assert err <= TOL, err
 
 
-def test_burst_beyond_one_time_table_chunk(pd, oracle_mod):
-    """300 nano steps with a time-dependent source: the kernel's table of source time
-    factors is refilled every 256 steps."""
-    err = burst_case(pd, oracle_mod, W.config2(n=5, m=9), 4, 0.5, 300, 0.2, 13)
+@pytest.mark.parametrize("lds", [False, True], ids=["auto", "lds"])
+def test_burst_beyond_one_time_table_chunk(pd, oracle_mod, lds):
+    """300 nano steps with a time-dependent source: the kernels' tables of source time
+    factors are refilled every 256 steps."""
+    err = burst_case(pd, oracle_mod, W.config2(n=5, m=9), 4, 0.5, 300, 0.2, 13, lds)
     say("300-step burst max rel err", err)
     assert err <= TOL, err
+
+
+def test_in_wave_and_lds_kernels_agree_on_the_config2_patch(pd):
+    """The two kernels on 17 x 17 patches (the benchmark's shape) over 40 nano steps agree
+    to rounding."""
+    prob = W.config2(n=9, m=17)
+    outs = []
+    for lds in (False, True):
+        g = pd.Grid(prob)
+        if lds:
+            g.set_option(pd.OPT_EXCHANGE, 1)
+        dt = 0.4 * g.query().dt_micro_limit
+        state, edge = g.lift_bc(g.initial())
+        g.micro_burst_upwind(state, edge, 0.02, dt, 40, 3, 0.0)
+        g.sync()
+        outs.append(state)
+    err = float((outs[0] - outs[1]).abs().max()) / max(1.0, float(outs[1].abs().max()))
+    say("in-wave vs LDS", err)
+    assert err <= 1e-13, err
 
 
 @pytest.mark.parametrize("conv", ["upwind", "central"])

@@ -112,6 +112,22 @@ __global__ void k_closure_features(Geo g, SrcInfo src, const double* __restrict_
 __device__ __forceinline__ float gelu_f(float x) {
   return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
 }
+// GELU for inference: erf by the rational-exponential form of Abramowitz and Stegun
+// (eq. 7.1.26, |error| <= 1.5e-7 on x >= 0, odd extension), with the hardware reciprocal and
+// base-2 exponential: about a third of the instructions of the library erf, and far below
+// the bfloat16 rounding the activations get next.
+__device__ __forceinline__ float gelu_infer(float x) {
+  const float z = fabsf(x) * 0.70710678118654752f;
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.0f));
+  float p = fmaf(1.061405429f, t, -1.453152027f);
+  p = fmaf(p, t, 1.421413741f);
+  p = fmaf(p, t, -0.284496736f);
+  p = fmaf(p, t, 0.254829592f);
+  p *= t;
+  const float e = __builtin_amdgcn_exp2f(-z * z * 1.4426950408889634f);
+  const float erfz = fmaf(-p, e, 1.0f);  // erf(|x| / sqrt 2)
+  return 0.5f * x * (1.0f + copysignf(erfz, x));
+}
 __device__ __forceinline__ float gelu_grad_f(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
          x * expf(-0.5f * x * x) * 0.39894228040143268f;
@@ -447,7 +463,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW& W, const unsigned short* xt
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int row = 32 * mt + 8 * (e / 4) + (lane >> 5) * 4 + (e & 3);
-      ht[row * CL_HID + col] = to_bf16(gelu_f(acc[t][e] + bias));
+      ht[row * CL_HID + col] = to_bf16(gelu_infer(acc[t][e] + bias));
     }
   }
   __syncthreads();
@@ -473,7 +489,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW& W, const unsigned short* xt
     const int col = 64 * nh + 32 * t + li;
     const float bias = W.par[CL_OB2 + col], w3 = from_bf16(W.w3[col]);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) rs[e] += gelu_f(acc[t][e] + bias) * w3;
+    for (int e = 0; e < 16; ++e) rs[e] += gelu_infer(acc[t][e] + bias) * w3;
   }
 #pragma unroll
   for (int e = 0; e < 16; ++e) {

@@ -128,15 +128,16 @@ __device__ int block_exclusive_scan(int v, int* scratch, int& total) {
 
 // One block: this step's spot-check segments (per instance, every stride-th item from a
 // hashed offset, at least one item), their prefix sums and total; clears the residuals.
-// Each thread takes a contiguous run of instances, so the prefix order is the instance
-// order.
+// Segment slots follow S.order (instances by descending item cost), so the queue hands
+// out the longest spot checks first; each thread takes a contiguous run of slots.
 __global__ __launch_bounds__(SEG_THREADS) void k_spot_segments(SpotArgs S) {
   __shared__ int scan[SEG_THREADS];
   const long long step = S.clk->base + S.k;
   const int per = (S.n + SEG_THREADS - 1) / SEG_THREADS;
   const int i0 = threadIdx.x * per, i1 = i0 + per < S.n ? i0 + per : S.n;
   int mine = 0;
-  for (int i = i0; i < i1; ++i) {
+  for (int sl = i0; sl < i1; ++sl) {
+    const int i = S.order[sl];
     const int cnt = S.count[i];
     unsigned int h = (unsigned int)(step * 2654435761ull) ^ (unsigned int)(i * 40503u + 17u);
     h ^= h >> 15;
@@ -149,15 +150,15 @@ __global__ __launch_bounds__(SEG_THREADS) void k_spot_segments(SpotArgs S) {
       c = 1;
       f = (int)(h % (unsigned int)cnt);
     }
-    S.spot[i] = make_int4(S.first[i] + f, c, S.stride, 0);
+    S.spot[sl] = make_int4(S.first[i] + f, c, S.stride, 0);
     S.resid[i] = 0u;
     mine += c;
   }
   int total;
   int run = block_exclusive_scan(mine, scan, total);
-  for (int i = i0; i < i1; ++i) {
-    S.spot[i].w = run;
-    run += S.spot[i].y;
+  for (int sl = i0; sl < i1; ++sl) {
+    S.spot[sl].w = run;
+    run += S.spot[sl].y;
   }
   if (threadIdx.x == 0) *S.spot_n = total;
 }
@@ -203,7 +204,8 @@ __global__ __launch_bounds__(SEG_THREADS) void k_redo_segments(SpotArgs S) {
   const int per = (S.n + SEG_THREADS - 1) / SEG_THREADS;
   const int i0 = threadIdx.x * per, i1 = i0 + per < S.n ? i0 + per : S.n;
   int mine = 0, bad = 0;
-  for (int i = i0; i < i1; ++i) {
+  for (int sl = i0; sl < i1; ++sl) {
+    const int i = S.order[sl];
     const float r = __uint_as_float(S.resid[i]);
     const bool redo = !((double)r <= S.threshold);
     mine += redo ? S.count[i] : 0;
@@ -213,10 +215,11 @@ __global__ __launch_bounds__(SEG_THREADS) void k_redo_segments(SpotArgs S) {
   int run = block_exclusive_scan(mine, scan, total);
   int nbad;
   (void)block_exclusive_scan(bad, scan, nbad);
-  for (int i = i0; i < i1; ++i) {
+  for (int sl = i0; sl < i1; ++sl) {
+    const int i = S.order[sl];
     const float r = __uint_as_float(S.resid[i]);
     const bool redo = !((double)r <= S.threshold);
-    S.redo[i] = make_int4(S.first[i], redo ? S.count[i] : 0, 1, run);
+    S.redo[sl] = make_int4(S.first[i], redo ? S.count[i] : 0, 1, run);
     run += redo ? S.count[i] : 0;
   }
   if (threadIdx.x == 0) {

@@ -274,6 +274,7 @@ struct BatchArgs {
 struct SpotArgs {
   const int* first;
   const int* count;
+  const int* order;         // instances by descending item cost: segment slot s is order[s]
   int n;                    // instances
   int stride;               // one item in `stride` is checked per step
   const Clock* clk;

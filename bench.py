@@ -486,6 +486,47 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def trace_avg_us(path, kernel):
+    """Average duration (us) of `kernel` in a committed kernel-table summary, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if not line.startswith("#") and kernel in line:
+                nums = line.split()[-6:]
+                try:
+                    return float(nums[1])
+                except (ValueError, IndexError):
+                    return None
+    return None
+
+
+def closure_kernel_roofline(n_patches):
+    """k_closure_step against its two roofs: bfloat16 MFMA for the network (2 x (33 x 128 +
+    128 x 128 + 128) flops per patch) and HBM (each patch's static table of 12 doubles,
+    its macro value read and written, F_hat written: 120 bytes), with the duration from
+    the committed rocprofv3 trace of the closure batch (the kernel runs inside the
+    closure graph, so it is not timed apart here) and the counters taken with it."""
+    stats = os.path.join(ROOT, "profiles", "k_closure_step_config5_kernel_stats.txt")
+    us = trace_avg_us(stats, "k_closure_step")
+    if us is None:
+        return None
+    flops = n_patches * 2.0 * (33 * 128 + 128 * 128 + 128)
+    nbytes = n_patches * 120.0
+    t = us * 1e-6
+    return {"kernel": "k_closure_step (features, bf16 MFMA network, projective update; "
+                      "one batch step)",
+            "duration_us": us, "duration_source": os.path.relpath(stats, ROOT),
+            "mfma": {"achieved_tflops": flops / t / 1e12, "peak_tflops": PEAK_MFMA_BF16 / 1e12,
+                     "frac": flops / t / PEAK_MFMA_BF16, "flops_per_launch": flops},
+            "hbm": {"achieved_gbs": nbytes / t / 1e9, "peak_gbs": 8000.0,
+                    "frac": nbytes / t / 8e12, "algorithmic_bytes": nbytes,
+                    "traffic": read_traffic("k_closure_step", "config5", "f64", "closure",
+                                            CLOSURE_SOURCES)},
+            "counters": read_counters("k_closure_step", "config5", "f64", "closure", t,
+                                      CLOSURE_SOURCES)}
+
+
 def closure_part(args, B, grids, stream, t_plain, ref, log):
     """Train the closure on plain-scheme pairs of disjoint instances and time the batch
     with it (spot checks on 1% of the work items per step, per-member fallback): rates,
@@ -537,6 +578,7 @@ def closure_part(args, B, grids, stream, t_plain, ref, log):
                      "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                      "generate_s": t_gen, "train_s": t_train},
         "dtype": "bf16 MFMA (fp32 accumulate) closure, f64 plain fallback",
+        "closure_kernel": closure_kernel_roofline(P),
     }
     return C, threshold, part
 
@@ -675,6 +717,8 @@ def bench_refresh(args):
         torch.cuda.synchronize()
         kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
         info = g.query()
+        if args.calibrate_copy:
+            calibration_copy(args.calibrate_copy)
         # the frozen-edge fused step on the same problem (autotuned, graph replay)
         gf = pd.Grid(prob)
         Uf = gf.initial()
@@ -711,7 +755,11 @@ def bench_refresh(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["f64"] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK["f64"], "traffic": None,
                      "kernel": KERNEL_NAME[info.exchange] + " (split mode: one sub-burst)",
-                     "kernel_ms": kern_s * 1e3, "flops_per_update": 20},
+                     "kernel_ms": kern_s * 1e3, "flops_per_update": 20,
+                     "counters": read_counters(
+                         KERNEL_NAME[info.exchange], "refresh", "f64",
+                         f"{info.exchange},{info.cols_per_lane},{info.rows_per_lane},"
+                         f"{info.patches_per_block}", kern_s)},
         "frozen_edge_fused_ms_per_step": t_fused * 1e3,
     }
     if not args.no_cpu_baseline:
@@ -780,6 +828,8 @@ def bench_adi(args):
             b.record(stream)
         torch.cuda.synchronize()
         kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+        if args.calibrate_copy:
+            calibration_copy(args.calibrate_copy)
     pts = info.n_points
     n_src = len(prob["src"])
     # per point and nano step: two tridiagonal rows (about 6 flops each), two explicit
@@ -803,10 +853,14 @@ def bench_adi(args):
         "roofline": {"bound": "alu", "achieved": flops_per_update * pts * n_t / kern_s / 1e12,
                      "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
                      "frac": flops_per_update * pts * n_t / kern_s / PEAK["f64"],
-                     "traffic": None, "algorithmic_bytes": alg_bytes,
+                     "traffic": read_traffic("k_burst_adi_r", "adi", "f64", "adi",
+                                             ADI_SOURCES),
+                     "algorithmic_bytes": alg_bytes,
                      "hbm_frac": alg_bytes / kern_s / 8e12,
-                     "kernel": "k_burst_adi (one ADI burst)", "kernel_ms": kern_s * 1e3,
-                     "flops_per_update": flops_per_update},
+                     "kernel": "k_burst_adi_r (register-line ADI burst)",
+                     "kernel_ms": kern_s * 1e3, "flops_per_update": flops_per_update,
+                     "counters": read_counters("k_burst_adi_r", "adi", "f64", "adi", kern_s,
+                                               ADI_SOURCES)},
     }
     if not args.no_cpu_baseline:
         # the oracle's ADI burst (numpy, dense line solves) on the first patches of the grid
@@ -917,7 +971,9 @@ def bench_upwind(args):
                      "kernel": f"k_burst_hux (in-wave, one {form} burst)",
                      "kernel_ms": kern_s * 1e3,
                      "kernel_ms_by_form": {k: v * 1e3 for k, v in kern.items()},
-                     "flops_per_update": flops_per_update},
+                     "flops_per_update": flops_per_update,
+                     "counters": read_counters("k_burst_hux", "upwind", "f64", "hux", kern_s,
+                                               HU_SOURCES)},
     }
     if not args.no_cpu_baseline:
         # the oracle's burst (numpy) on the first patches of the grid
@@ -1043,7 +1099,9 @@ def bench_full_domain(args):
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": peak / 1e9,
                      "unit": "GB/s", "frac": achieved / peak,
                      "traffic": traffic, "algorithmic_bytes": alg_bytes,
-                     "kernel": "k_fd_step (one lattice step)", "kernel_ms": kern_s * 1e3},
+                     "kernel": "k_fd_step (one lattice step)", "kernel_ms": kern_s * 1e3,
+                     "counters": read_counters("k_fd_step", "full-domain", "f64", "fd", kern_s,
+                                               FD_SOURCES)},
         "vs_patch_dynamics": {
             "T": T_end, "fd_steps": fd_steps, "fd_time_s": fd_steps * el / K,
             "pd_macro_steps": prob["time"]["n_steps"], "pd_time_s": t_pd,
@@ -1151,6 +1209,16 @@ def main():
                                                       kern == "k_batch" else ""),
                         args.counter_last, counter_file(kern, args.workload, args.precision),
                         args.pmc_command, args.workload, args.precision, args.pmc_shape, files)
+        return
+    if args.pmc_summary and args.counter_kernel:
+        kern = args.counter_kernel
+        files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
+                 "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
+                 "k_fd_step": FD_SOURCES}.get(kern)
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1],
+                    kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
+                    args.calibrate_copy or 256, traffic_file(kern, args.workload, args.precision),
+                    args.pmc_command, args.workload, args.precision, args.pmc_shape, files)
         return
     if args.pmc_summary:
         if args.workload == "full-domain":

@@ -158,11 +158,21 @@ def calibration_copy(mib):
     del src, dst
 
 
-def stats_summary(csv_path, out, title, command, top=14):
+def short_kernel_name(name):
+    """A demangled kernel name without its namespace, return type and parameter list."""
+    name = name.replace("pdk::(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0] if not name.startswith("(") else name
+
+
+def stats_summary(csv_path, out, title, command, top=20):
     """A rocprofv3 --stats kernel table (kernel_stats.csv) as a short text summary."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows:
+        r["Name"] = short_kernel_name(r["Name"])
     with open(out, "w") as fh:
         for line in title.strip().splitlines():
             fh.write(f"# {line}\n")
@@ -673,6 +683,15 @@ def bench_headline(args, workload_name="config4+config5"):
     print(json.dumps(out), flush=True)
 
 
+def fix_shape(pd, g, shape):
+    """Fixes the burst's launch shape from "exchange,cols,rows,patches_per_block"."""
+    xch, cols, rows, ppb = (int(v) for v in shape.split(","))
+    g.set_option(pd.OPT_EXCHANGE, xch)
+    g.set_option(pd.OPT_COLS_PER_LANE, cols)
+    g.set_option(pd.OPT_ROWS_PER_LANE, rows)
+    g.set_option(pd.OPT_PATCHES_PER_BLOCK, ppb)
+
+
 def bench_refresh(args):
     """Config-2 macro steps with the edge data refreshed between sub-bursts
     (pd_macro_step_refresh), against the frozen-edge fused step of the same problem."""
@@ -691,7 +710,11 @@ def bench_refresh(args):
         U = g.initial()
         V = g.new_U()
         # the sub-bursts run on the grid's launch shape (split mode), tuned on the fused step
-        tuned_ms = None if args.no_autotune else g.autotune(U, reps=5)
+        tuned_ms = None
+        if args.shape:
+            fix_shape(pd, g, args.shape)
+        elif not args.no_autotune:
+            tuned_ms = g.autotune(U, reps=5)
         for s in range(args.warmup):
             g.macro_step_refresh(U, t["t0"] + s * t["dt_macro"], Q, out=V)
             U, V = V, U
@@ -753,13 +776,11 @@ def bench_refresh(args):
                               "patches_per_block": info.patches_per_block,
                               "block_threads": info.block_threads, "tuned_ms": tuned_ms}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["f64"] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK["f64"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["f64"], "traffic": traffic,
                      "kernel": KERNEL_NAME[info.exchange] + " (split mode: one sub-burst)",
                      "kernel_ms": kern_s * 1e3, "flops_per_update": 20,
-                     "counters": read_counters(
-                         KERNEL_NAME[info.exchange], "refresh", "f64",
-                         f"{info.exchange},{info.cols_per_lane},{info.rows_per_lane},"
-                         f"{info.patches_per_block}", kern_s)},
+                     "counters": read_counters(KERNEL_NAME[info.exchange], "refresh", "f64",
+                                               shape, kern_s)},
         "frozen_edge_fused_ms_per_step": t_fused * 1e3,
     }
     if not args.no_cpu_baseline:
@@ -1185,6 +1206,9 @@ def main():
                     help="kernel name as in profiles/ (k_burst_x, k_batch, k_closure_step, ...)")
     ap.add_argument("--counter-last", type=int, default=0,
                     help="summarise only the last N dispatches of the kernel in each CSV")
+    ap.add_argument("--counter-match", default="",
+                    help="kernel-name substring selecting the dispatches summarised (default: "
+                         "the --counter-kernel name), e.g. one template instance")
     ap.add_argument("--pmc-shape", default="", help="launch shape the counters were taken at")
     ap.add_argument("--pmc-command", default="", help="command that produced the counters")
     args = ap.parse_args()
@@ -1205,8 +1229,8 @@ def main():
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
                  "k_fd_step": FD_SOURCES}.get(kern)
-        counter_summary(args.counter_summary, kern + ("<" if kern.startswith("k_burst") or
-                                                      kern == "k_batch" else ""),
+        counter_summary(args.counter_summary, args.counter_match or
+                        kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                         args.counter_last, counter_file(kern, args.workload, args.precision),
                         args.pmc_command, args.workload, args.precision, args.pmc_shape, files)
         return
@@ -1215,7 +1239,7 @@ def main():
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
                  "k_fd_step": FD_SOURCES}.get(kern)
-        pmc_summary(args.pmc_summary[0], args.pmc_summary[1],
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.counter_match or
                     kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                     args.calibrate_copy or 256, traffic_file(kern, args.workload, args.precision),
                     args.pmc_command, args.workload, args.precision, args.pmc_shape, files)
@@ -1273,11 +1297,7 @@ def main():
         U = g.initial()
         tuned_ms = None
         if args.shape:
-            xch, cols, rows, ppb = (int(v) for v in args.shape.split(","))
-            g.set_option(pd.OPT_EXCHANGE, xch)
-            g.set_option(pd.OPT_COLS_PER_LANE, cols)
-            g.set_option(pd.OPT_ROWS_PER_LANE, rows)
-            g.set_option(pd.OPT_PATCHES_PER_BLOCK, ppb)
+            fix_shape(pd, g, args.shape)
         elif not args.no_autotune:
             tuned_ms = g.autotune(U, reps=5)
         # set-up: one graph replay (16 steps) instantiates the solve graph on this field

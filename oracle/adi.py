@@ -15,8 +15,17 @@ with the source at the half step:
 Each implicit half step is a set of 1-D systems (rows, then columns); here they are built
 by applying the affine operator to unit vectors and solved densely (numpy), which is slow
 and plainly what the equations say.
+
+Sec. 4.1.2 runs the same micro solver with the 3-point and 4-point upwind first
+differences in place of the 2-point one.  With `points` given, each half operator takes
+the first difference of that form (oracle/upwind.py: the printed formula where the
+velocity component is >= 0, its mirror image where it is < 0, the edge data through two
+ghost layers); the implicit lines are then banded (two neighbours on each side) and are
+solved densely like the tridiagonal ones.
 """
 import numpy as np
+
+from oracle import upwind
 
 
 def _parts(coef, p, mx, me):
@@ -49,6 +58,20 @@ def op_eta(u, gamma, om, phi, gem, gep, de, central):
     return op_xi(u.T, gamma.T, om.T, phi.T, gem, gep, de, central).T
 
 
+def op_xi_p(u, alpha, nu, phi, gxm, gxp, dx, points, r):
+    """L_xi u with the p-point upwind first difference of Sec. 4.1.2 (affine: the two
+    ghost layers of edge data included): alpha d2_xi u - nu d_xi u + phi/2 u."""
+    me = u.shape[0]
+    e = upwind.extend(u, gxm[:me], gxp[:me], dx)
+    return (alpha * upwind.second_difference(e, dx)
+            - nu * upwind.first_difference(e, nu, dx, points, r) + 0.5 * phi * u)
+
+
+def op_eta_p(u, gamma, om, phi, gem, gep, de, points, r):
+    """L_eta u with the p-point upwind first difference, by transposition."""
+    return op_xi_p(u.T, gamma.T, om.T, phi.T, gem, gep, de, points, r).T
+
+
 def _solve_lines(apply, rhs, h):
     """Solve (I - h A) x = rhs for the affine line operator apply(x) = A x + c, line by
     line (rows of rhs): the matrix from unit vectors, then a dense solve."""
@@ -66,11 +89,14 @@ def _solve_lines(apply, rhs, h):
     return out
 
 
-def adi_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
+def adi_burst(grid, coef, u, edge, t_n, dt, n_t, tfac, points=None, r=0.5):
     """n_t Peaceman-Rachford nano steps of every patch (the ADI micro solver of
     Sec. 4.1.1).  grid: dict with h_xi, h_eta,
     m_xi, m_eta, conv; coef [5 + n_src][P][me][mx]; u [P][me][mx] (not modified);
-    edge [P][4][M] (xi-, xi+, eta-, eta+); tfac(t) -> the source time factors."""
+    edge [P][4][M] (xi-, xi+, eta-, eta+); tfac(t) -> the source time factors.
+    points = 2, 3 or 4: the first differences of that upwind form (Sec. 4.1.2; r is the
+    4-point form's parameter) whatever the grid's convection option; None: the grid's own
+    2-point upwind or central differences."""
     mx, me = grid["m_xi"], grid["m_eta"]
     dx, de = grid["h_xi"] / (mx - 1), grid["h_eta"] / (me - 1)
     central = grid["conv"] == "central"
@@ -83,8 +109,12 @@ def adi_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
             th = t_n + s * dt + 0.5 * dt
             T = tfac(th)
             src = sum((T[q] * S[q] for q in range(len(S))), np.zeros_like(v))
-            Lx = lambda w: op_xi(w, al, nu, ph, gxm, gxp, dx, central)
-            Le = lambda w: op_eta(w, ga, om, ph, gem, gep, de, central)
+            if points is None:
+                Lx = lambda w: op_xi(w, al, nu, ph, gxm, gxp, dx, central)
+                Le = lambda w: op_eta(w, ga, om, ph, gem, gep, de, central)
+            else:
+                Lx = lambda w: op_xi_p(w, al, nu, ph, gxm, gxp, dx, points, r)
+                Le = lambda w: op_eta_p(w, ga, om, ph, gem, gep, de, points, r)
             r1 = v + 0.5 * dt * Le(v) + 0.5 * dt * src
             ustar = _solve_lines(Lx, r1, 0.5 * dt)
             r2 = ustar + 0.5 * dt * Lx(ustar) + 0.5 * dt * src
@@ -93,9 +123,10 @@ def adi_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
     return out
 
 
-def fe_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
+def fe_burst(grid, coef, u, edge, t_n, dt, n_t, tfac, points=None, r=0.5):
     """Forward Euler with the same operator, step (iii) of Sec. 3.3 (cross-check of the
-    operator against the C oracle's explicit burst)."""
+    operator against the C oracle's explicit burst, and with `points` against the
+    explicit burst of the higher-order upwind forms)."""
     mx, me = grid["m_xi"], grid["m_eta"]
     dx, de = grid["h_xi"] / (mx - 1), grid["h_eta"] / (me - 1)
     central = grid["conv"] == "central"
@@ -107,8 +138,13 @@ def fe_burst(grid, coef, u, edge, t_n, dt, n_t, tfac):
         for s in range(n_t):
             T = tfac(t_n + s * dt)
             src = sum((T[q] * S[q] for q in range(len(S))), np.zeros_like(v))
-            v = v + dt * (op_xi(v, al, nu, ph, gxm, gxp, dx, central)
-                          + op_eta(v, ga, om, ph, gem, gep, de, central) + src)
+            if points is None:
+                Lv = (op_xi(v, al, nu, ph, gxm, gxp, dx, central)
+                      + op_eta(v, ga, om, ph, gem, gep, de, central))
+            else:
+                Lv = (op_xi_p(v, al, nu, ph, gxm, gxp, dx, points, r)
+                      + op_eta_p(v, ga, om, ph, gem, gep, de, points, r))
+            v = v + dt * (Lv + src)
         out[p] = v
     return out
 

@@ -52,6 +52,7 @@ BURST_SOURCES = ["pd_burst.inc", "pd_internal.h"] + [
 FD_SOURCES = ["pd_fd.hip", "pd_internal.h"]
 HU_SOURCES = ["pd_upwind.hip", "pd_internal.h"]
 ADI_SOURCES = ["pd_adi.hip", "pd_internal.h"]
+ADU_SOURCES = ["pd_adi_upwind.hip", "pd_internal.h"]
 
 
 def burst_source_hash(files=None):
@@ -758,6 +759,8 @@ def bench_refresh(args):
     per_step = W.updates_per_step(prob)
     sub_updates = info.n_points * n_sub
     achieved = 20 * sub_updates / kern_s
+    shape = f"{info.exchange},{info.cols_per_lane},{info.rows_per_lane},{info.patches_per_block}"
+    traffic = read_traffic(KERNEL_NAME[info.exchange], "refresh", "f64", shape)
     out = {
         "metric": "patch-point updates/s (and macro steps/s) with the edge data refreshed "
                   "during the burst",
@@ -803,15 +806,19 @@ def bench_refresh(args):
 
 
 def bench_adi(args):
-    """Sec. 4.1.1's setup with the ADI micro solver (sine map lambda = 0.1, D = 1,
-    v = (10x, 10y), f = 20, h = 1e-3, tau = 1e-6, 10 micro intervals, n_t = 2) on a
-    GPU-sized macro grid: lift and edge data, ADI burst, restriction, projective step."""
+    """The ADI micro solver on a GPU-sized macro grid (sine map lambda = 0.1, f = 20,
+    h = 1e-3, tau = 1e-6, 10 micro intervals, n_t = 2): lift and edge data, ADI burst,
+    restriction, projective step.  adi: Sec. 4.1.1's setup (D = 1, v = (10x, 10y), 2-point
+    upwind); adi-upwind: Sec. 4.1.2's (D = 1 + x, v = (1 + 10x, 10y)) with the 3- or
+    4-point upwind first differences in the ADI solver."""
     import torch
 
     from paper_2405_08764_amd import pd
     from paper_2405_08764_amd import workloads as W
     n = args.adi_n
-    prob = W.paper_cdr(1, lam=0.1, n=n, m=11)
+    hu = args.workload == "adi-upwind"
+    points, r = args.upwind_points, args.upwind_r
+    prob = W.paper_cdr(2 if hu else 1, lam=0.1, n=n, m=11)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     K = args.steps
@@ -822,9 +829,15 @@ def bench_adi(args):
         t = prob["time"]
         dt, n_t = t["dt_micro"], t["n_t"]
 
+        def burst(state, edge, tn):
+            if hu:
+                g.micro_burst_adi_upwind(state, edge, tn, dt, n_t, points, r)
+            else:
+                g.micro_burst_adi(state, edge, tn, dt, n_t)
+
         def step(U, tn):
             state, edge = g.lift_bc(U)
-            g.micro_burst_adi(state, edge, tn, dt, n_t)
+            burst(state, edge, tn)
             return g.macro_step(U, tn, dt_macro=dtm, dt_micro=dt, n_t=n_t,
                                 Ubar=g.restrict(state))
 
@@ -845,7 +858,7 @@ def bench_adi(args):
                for _ in range(args.kernel_reps)]
         for a, b in evs:
             a.record(stream)
-            g.micro_burst_adi(state, edge, 0.0, dt, n_t)
+            burst(state, edge, 0.0)
             b.record(stream)
         torch.cuda.synchronize()
         kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
@@ -853,35 +866,52 @@ def bench_adi(args):
             calibration_copy(args.calibrate_copy)
     pts = info.n_points
     n_src = len(prob["src"])
-    # per point and nano step: two tridiagonal rows (about 6 flops each), two explicit
-    # half-operator evaluations (about 8 each), the source (2 per term each half), the
-    # Thomas forward and backward passes (about 5 each)
-    flops_per_update = 2 * (6 + 8 + 2 * n_src + 5)
+    if hu:
+        # per point and nano step, each half: the explicit 5-point operator across the
+        # line (10), the five band entries (10), the source (2 per term), the banded
+        # elimination (about 16) and back substitution (4)
+        flops_per_update = 2 * (10 + 10 + 2 * n_src + 16 + 4)
+        kern, files, shape = "k_burst_adi_hu", ADU_SOURCES, f"p{points}"
+        desc = (f"adi-upwind: Sec. 4.1.2 problem (sine map lambda 0.1, D = 1 + x, "
+                f"v = (1 + 10x, 10y), f = 20, exact e^(x+y+t)) on {n}x{n} macro nodes, "
+                f"11x11 micro points, h = 1e-3, tau = 1e-6, n_t = 2 ADI steps with the "
+                f"{points}-point upwind first differences" + (f" (r = {r})" if points == 4
+                                                               else "") +
+                ", dt_macro at 0.4 of the macro bound")
+        ktxt = "k_burst_adi_hu (banded ADI burst)"
+    else:
+        # per point and nano step: two tridiagonal rows (about 6 flops each), two explicit
+        # half-operator evaluations (about 8 each), the source (2 per term each half), the
+        # Thomas forward and backward passes (about 5 each)
+        flops_per_update = 2 * (6 + 8 + 2 * n_src + 5)
+        kern, files, shape = "k_burst_adi_r", ADI_SOURCES, "adi"
+        desc = (f"adi: Sec. 4.1.1 problem (sine map lambda 0.1, D = 1, v = (10x, 10y), "
+                f"f = 20, exact e^(x+y+t)) on {n}x{n} macro nodes, 11x11 micro points, "
+                f"h = 1e-3, tau = 1e-6, n_t = 2 ADI steps, dt_macro at 0.4 of the macro bound")
+        ktxt = "k_burst_adi_r (register-line ADI burst)"
     alg_bytes = pts * 8 * (2 + 5 + n_src) + info.n_patches * 4 * info.m_xi * 8
     out = {
-        "metric": "patch-point updates/s of the ADI micro burst (Sec. 4.1.1 setup)",
+        "metric": "patch-point updates/s of the ADI micro burst (Sec. 4.1.2 setup, higher-"
+                  "order upwind)" if hu else
+                  "patch-point updates/s of the ADI micro burst (Sec. 4.1.1 setup)",
         "value": pts * n_t * K / el, "unit": "patch-point updates/s",
         "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": el / K * 1e3,
         "macro_steps_per_s": K / el,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (the paper's analytic coefficients, no dataset)",
-        "config": {"workload": f"adi: Sec. 4.1.1 problem (sine map lambda 0.1, D = 1, "
-                               f"v = (10x, 10y), f = 20, exact e^(x+y+t)) on {n}x{n} macro "
-                               f"nodes, 11x11 micro points, h = 1e-3, tau = 1e-6, n_t = 2 "
-                               f"ADI steps, dt_macro at 0.4 of the macro bound",
+        "config": {"workload": desc,
                    "patches": info.n_patches, "dt_macro": dtm,
                    "dt_micro_over_explicit_bound": dt / info.dt_micro_limit},
         "roofline": {"bound": "alu", "achieved": flops_per_update * pts * n_t / kern_s / 1e12,
                      "peak": PEAK["f64"] / 1e12, "unit": "TFLOP/s",
                      "frac": flops_per_update * pts * n_t / kern_s / PEAK["f64"],
-                     "traffic": read_traffic("k_burst_adi_r", "adi", "f64", "adi",
-                                             ADI_SOURCES),
+                     "traffic": read_traffic(kern, args.workload, "f64", shape, files),
                      "algorithmic_bytes": alg_bytes,
                      "hbm_frac": alg_bytes / kern_s / 8e12,
-                     "kernel": "k_burst_adi_r (register-line ADI burst)",
+                     "kernel": ktxt,
                      "kernel_ms": kern_s * 1e3, "flops_per_update": flops_per_update,
-                     "counters": read_counters("k_burst_adi_r", "adi", "f64", "adi", kern_s,
-                                               ADI_SOURCES)},
+                     "counters": read_counters(kern, args.workload, "f64", shape, kern_s,
+                                               files)},
     }
     if not args.no_cpu_baseline:
         # the oracle's ADI burst (numpy, dense line solves) on the first patches of the grid
@@ -892,7 +922,7 @@ def bench_adi(args):
         u0, e = o.lift(Uo)[:npat], o.edge(Uo)[:npat]
         s0 = time.perf_counter()
         adi.adi_burst(prob["grid"], o.coef[:, :npat], u0, e, 0.0, dt, n_t,
-                      adi.time_factors(prob))
+                      adi.time_factors(prob), *((points, r) if hu else ()))
         el_c = time.perf_counter() - s0
         out["cpu_baseline"] = {"value": npat * info.m_xi * info.m_eta * n_t / el_c,
                                "unit": "patch-point updates/s", "cores": 1, "kind": "oracle",
@@ -1146,7 +1176,8 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--workload", default="headline",
                     choices=["headline", "config1", "config2", "config3", "config4",
-                             "config5", "full-domain", "refresh", "adi", "upwind"])
+                             "config5", "full-domain", "refresh", "adi", "adi-upwind",
+                             "upwind"])
     ap.add_argument("--batch-shapes", default=None, metavar="JSON",
                     help="config4/5 and headline: read the batch launch shapes from this "
                          "file if it exists (no autotuning), else autotune and write it")
@@ -1160,9 +1191,10 @@ def main():
     ap.add_argument("--adi-n", type=int, default=129,
                     help="adi: macro nodes per side")
     ap.add_argument("--upwind-points", type=int, default=3, choices=[2, 3, 4],
-                    help="upwind: the micro first difference (2-, 3- or 4-point)")
+                    help="upwind, adi-upwind: the micro first difference (2-, 3- or "
+                         "4-point)")
     ap.add_argument("--upwind-r", type=float, default=0.5,
-                    help="upwind: r of the 4-point difference")
+                    help="upwind, adi-upwind: r of the 4-point difference")
     ap.add_argument("--refresh", type=int, default=5,
                     help="refresh: sub-bursts per macro step (edge data refreshed between)")
     ap.add_argument("--fd-n", type=int, default=4097,
@@ -1214,7 +1246,8 @@ def main():
     args = ap.parse_args()
     if args.steps is None:
         args.steps = {"headline": 20, "config4": 20, "config5": 20, "full-domain": 400,
-                      "refresh": 200, "adi": 200, "upwind": 200}.get(args.workload, 1000)
+                      "refresh": 200, "adi": 200, "adi-upwind": 200,
+                      "upwind": 200}.get(args.workload, 1000)
     if args.warmup is None:
         args.warmup = {"headline": 3, "config4": 3, "config5": 3, "config1": 32,
                        "config2": 32, "config3": 32}.get(args.workload, 4)
@@ -1228,7 +1261,7 @@ def main():
         kern = args.counter_kernel
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
-                 "k_fd_step": FD_SOURCES}.get(kern)
+                 "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES}.get(kern)
         counter_summary(args.counter_summary, args.counter_match or
                         kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                         args.counter_last, counter_file(kern, args.workload, args.precision),
@@ -1238,7 +1271,7 @@ def main():
         kern = args.counter_kernel
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
-                 "k_fd_step": FD_SOURCES}.get(kern)
+                 "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES}.get(kern)
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.counter_match or
                     kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                     args.calibrate_copy or 256, traffic_file(kern, args.workload, args.precision),
@@ -1284,7 +1317,7 @@ def main():
         return bench_full_domain(args)
     if args.workload == "refresh":
         return bench_refresh(args)
-    if args.workload == "adi":
+    if args.workload in ("adi", "adi-upwind"):
         return bench_adi(args)
     if args.workload == "upwind":
         return bench_upwind(args)

@@ -203,6 +203,26 @@ pd_status pd_micro_burst_adi(pd_grid g, double* patch_state, const double* edge,
 pd_status pd_micro_burst_upwind(pd_grid g, double* patch_state, const double* edge,
                                 double t_n, double dt_micro, int32_t n_t, int32_t points,
                                 double r, void* stream);
+/* Step (iii) with the ADI micro solver of pd_micro_burst_adi and the first differences of
+ * pd_micro_burst_upwind (Sec. 4.1.2 ran its micro simulations with that solver and tried
+ * the 3- and 4-point upwind forms in it): n_t Peaceman-Rachford nano steps of size
+ * dt_micro from t_n,
+ *   (I - dt/2 L_xi)  u*      = (I + dt/2 L_eta) u^n + dt/2 s(t + dt/2),
+ *   (I - dt/2 L_eta) u^{n+1} = (I + dt/2 L_xi)  u*  + dt/2 s(t + dt/2),
+ * L_xi = alpha d2_xi - nu d_xi + phi/2 and L_eta likewise, d_xi and d_eta of the given
+ * form (points 2, 3 or 4, parameter r, mirrored where the velocity component is < 0,
+ * whatever the grid's convection option), the edge gradients of edge [P][4][M] through the
+ * two ghost layers of pd_micro_burst_upwind.  The implicit lines are banded (two
+ * neighbours on each side) and are eliminated without pivoting: stable while every line
+ * matrix is diagonally dominant (3-point form: dt/2 (|nu| / d_xi + phi/2) <= 1, likewise
+ * along eta); a non-finite result sets the flag pd_sync reports.  patch_state
+ * [P][m_eta][m_xi] FP64 is updated in place.  PD_EINVAL for dt_micro <= 0, n_t < 1,
+ * points outside 2..4, non-finite r, or 8 m_xi m_eta + 4 max(m_xi, m_eta) > 8192 (a patch,
+ * its band rows and its edge data in 64 KiB of LDS; m up to 31 for square patches);
+ * PD_ESTATE before coefficients are set. */
+pd_status pd_micro_burst_adi_upwind(pd_grid g, double* patch_state, const double* edge,
+                                    double t_n, double dt_micro, int32_t n_t, int32_t points,
+                                    double r, void* stream);
 /* Step (iv): eq. (Restriction) by the composite trapezoidal rule, Ubar[P]. */
 pd_status pd_restrict(pd_grid g, const double* patch_state, double* Ubar, void* stream);
 /* Steps (v)-(vi): U_np1 = U_n + dt_macro (Ubar - U_n)/tau at patch nodes, Dirichlet data

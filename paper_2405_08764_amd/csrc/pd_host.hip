@@ -35,6 +35,14 @@ PD_DECL(hs_f64)
 PD_DECL(hs_f32)
 #undef PD_DECL
 
+// ADI burst with the higher-order upwind differences (pd_adi_upwind.hip): patches per
+// wave and LDS bytes for m_xi x m_eta patches (ppb = 0 when none fits), and the launcher.
+void adu_shape(int mx, int me, int& ppb, size_t& lds);
+hipError_t launch_burst_adi_hu(const Geo& g, const SrcInfo& src, const double* coef,
+                               long long plane, double* state, const double* edge, double t_n,
+                               double dt, int n_t, int points, double r, int* flag,
+                               hipStream_t s);
+
 // The burst kernel of one exchange family, precision and mode (fused macro step or
 // split-mode burst on caller-owned patch states); every family runs both modes.
 hipError_t launch_burst(int precision, int R, int C, int xch, int mode, const BurstArgs& a,
@@ -669,6 +677,31 @@ pd_status pd_micro_burst_adi(pd_grid g, double* state, const double* edge, doubl
   HIPCHK(hipSetDevice(g->d.device));
   HIPCHK(launch_burst_adi(g->g, g->src, g->coef(), (long long)g->g.P * g->g.m_xi * g->g.m_eta,
                           state, edge, t_n, dt, n_t, g->flag(), static_cast<hipStream_t>(stream)));
+  return PD_OK;
+}
+
+pd_status pd_micro_burst_adi_upwind(pd_grid g, double* state, const double* edge,
+                                    double t_n, double dt, int32_t n_t, int32_t points,
+                                    double r, void* stream) {
+  pd_status st = need_ws(g);  // no explicit-burst launch shape needed
+  if (st) return st;
+  if (!g->coeffs_set) return fail(PD_ESTATE, "coefficients not set");
+  if (!state || !edge) return fail(PD_EINVAL, "null argument");
+  if (!(dt > 0.0) || n_t < 1) return fail(PD_EINVAL, "dt_micro must be > 0 and n_t >= 1");
+  if (points < 2 || points > 4) return fail(PD_EINVAL, "points must be 2, 3 or 4");
+  if (!std::isfinite(r)) return fail(PD_EINVAL, "r must be finite");
+  {
+    int ppb = 0;
+    size_t lds = 0;
+    adu_shape(g->g.m_xi, g->g.m_eta, ppb, lds);
+    if (ppb < 1)
+      return fail(PD_EINVAL,
+                  "the ADI upwind burst needs 8 m_xi m_eta + 4 max(m_xi, m_eta) <= 8192");
+  }
+  HIPCHK(hipSetDevice(g->d.device));
+  HIPCHK(launch_burst_adi_hu(g->g, g->src, g->coef(),
+                             (long long)g->g.P * g->g.m_xi * g->g.m_eta, state, edge, t_n, dt,
+                             n_t, points, r, g->flag(), static_cast<hipStream_t>(stream)));
   return PD_OK;
 }
 

@@ -119,6 +119,9 @@ EXPORTS = {
     "pd_micro_burst_upwind": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                           C.c_double, C.c_int32, C.c_int32, C.c_double,
                                           C.c_void_p]),
+    "pd_micro_burst_adi_upwind": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                              C.c_double, C.c_int32, C.c_int32, C.c_double,
+                                              C.c_void_p]),
     "pd_restrict": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pd_macro_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                   C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -436,6 +439,12 @@ class Grid:
         _check(self.L.pd_micro_burst_upwind(self.h, self._state(state), self._edge(edge), float(t_n),
                                             float(dt), int(n_t), int(points), float(r),
                                             _stream()))
+        return state
+
+    def micro_burst_adi_upwind(self, state, edge, t_n, dt, n_t, points=3, r=0.5):
+        _check(self.L.pd_micro_burst_adi_upwind(self.h, self._state(state), self._edge(edge),
+                                                float(t_n), float(dt), int(n_t), int(points),
+                                                float(r), _stream()))
         return state
 
     def restrict(self, state):

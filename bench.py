@@ -167,20 +167,22 @@ def short_kernel_name(name):
     return name.split("(")[0] if not name.startswith("(") else name
 
 
-def stats_summary(csv_path, out, title, command, top=20):
-    """A rocprofv3 --stats kernel table (kernel_stats.csv) as a short text summary."""
+def stats_summary(csv_path, out, title, command, top=20, keep=""):
+    """A rocprofv3 --stats kernel table (kernel_stats.csv) as a short text summary: the
+    `top` kernels by total time, and every kernel whose name contains `keep`."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     for r in rows:
         r["Name"] = short_kernel_name(r["Name"])
+    rows = [r for k, r in enumerate(rows) if k < top or (keep and keep in r["Name"])]
     with open(out, "w") as fh:
         for line in title.strip().splitlines():
             fh.write(f"# {line}\n")
         fh.write(f"# command:\n#   {command}\n")
         fh.write(f"{'kernel':<66} {'calls':>6} {'avg_us':>12} {'min_us':>12} {'max_us':>12} "
                  f"{'total_ms':>12} {'pct':>7}\n")
-        for r in rows[:top]:
+        for r in rows:
             fh.write(f"{r['Name'][:66]:<66} {int(r['Calls']):>6} "
                      f"{float(r['AverageNs']) / 1e3:>12.2f} {float(r['MinNs']) / 1e3:>12.2f} "
                      f"{float(r['MaxNs']) / 1e3:>12.2f} {float(r['TotalDurationNs']) / 1e6:>12.3f} "
@@ -1255,7 +1257,7 @@ def main():
         ap.error("--steps must be >= 1 and --warmup >= 0")
     if args.stats_summary:
         stats_summary(args.stats_summary[0], args.stats_summary[1], args.stats_title,
-                      args.pmc_command)
+                      args.pmc_command, keep=args.counter_match)
         return
     if args.counter_summary:
         kern = args.counter_kernel

@@ -217,9 +217,9 @@ pd_status pd_micro_burst_upwind(pd_grid g, double* patch_state, const double* ed
  * matrix is diagonally dominant (3-point form: dt/2 (|nu| / d_xi + phi/2) <= 1, likewise
  * along eta); a non-finite result sets the flag pd_sync reports.  patch_state
  * [P][m_eta][m_xi] FP64 is updated in place.  PD_EINVAL for dt_micro <= 0, n_t < 1,
- * points outside 2..4, non-finite r, or 8 m_xi m_eta + 4 max(m_xi, m_eta) > 8192 (a patch,
- * its band rows and its edge data in 64 KiB of LDS; m up to 31 for square patches);
- * PD_ESTATE before coefficients are set. */
+ * points outside 2..4, non-finite r, or 5 m_xi m_eta + 4 max(m_xi, m_eta) > 8192 (a patch's
+ * two field planes, its eliminated rows and its edge data in 64 KiB of LDS; m up to 40
+ * for square patches); PD_ESTATE before coefficients are set. */
 pd_status pd_micro_burst_adi_upwind(pd_grid g, double* patch_state, const double* edge,
                                     double t_n, double dt_micro, int32_t n_t, int32_t points,
                                     double r, void* stream);

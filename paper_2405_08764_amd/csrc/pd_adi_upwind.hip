@@ -11,20 +11,26 @@
 // u_m = u_{m-2} + 2 dp g+, u_{m+1} = u_{m-3} + 4 dp g+.  Folding the ghosts onto the points
 // they mirror keeps every implicit line banded with two neighbours on each side.
 //
-// One wave holds several patches in LDS.  Each half step first assembles every point's
-// five band entries and right-hand side (all lanes, coefficient planes from HBM), then
-// lane l eliminates row l (first half) or lane k column k (second half): banded Gaussian
-// elimination without pivoting, the two rows below the pivot row carried in registers,
-// one reciprocal per row, then the back substitution.  Without pivoting the elimination
-// is stable while every line matrix is diagonally dominant; for the 3-point form that
-// holds when dt/2 (|nu| / d_xi + phi/2) <= 1 (likewise along eta), e.g. about 0.03 on the
-// paper's Sec. 4.1.2 patches.
+// One wave holds several patches; lane j of a patch owns line j (row j in the first half
+// step, column j in the second).  It walks its line point by point: loads the point's
+// coefficients, forms the five band entries and the right-hand side (the explicit half
+// operator across the line reads the other lines' values from LDS), eliminates the
+// entries left of the diagonal with the two rows above, already normalised and carried in
+// registers, and normalises the row by one reciprocal (banded Gaussian elimination
+// without pivoting, fused into the assembly).  The normalised rows go to LDS for the back
+// substitution, which writes the line's solution into the other field plane.  Without
+// pivoting the elimination is stable while every line matrix is diagonally dominant; for
+// the 3-point form that holds when dt/2 (|nu| / d_xi + phi/2) <= 1 (likewise along eta),
+// e.g. about 0.03 on the paper's Sec. 4.1.2 patches.
 #include "pd_internal.h"
 
 namespace pdk {
 
 // LDS of one wave's patches (at most 64 KiB).
 constexpr size_t ADU_LDS_MAX = 65536;
+// Per patch in LDS: the field planes u^n / u^{n+1} and u*, the normalised rows (upper
+// factors U1, U2 and right-hand side Y), the edge data.
+constexpr int ADU_PLANES = 5;
 
 namespace {
 
@@ -41,34 +47,36 @@ struct AduArgs {
   int* flag;
 };
 
-// Per patch in LDS: u, u*, the five band planes (offsets -2..2), the right-hand sides,
-// the edge data.
-constexpr int ADU_PLANES = 8;
+// First-difference weights at offsets -2..2 times the spacing, backward side (the
+// printed forms).
+__device__ inline void d1_unit(int points, double r, double (&c)[5]) {
+  c[0] = c[1] = c[2] = c[3] = c[4] = 0.0;
+  if (points == 2) {
+    c[2] = 1.0;
+    c[1] = -1.0;
+  } else if (points == 3) {
+    c[2] = 1.5;
+    c[1] = -2.0;
+    c[0] = 0.5;
+  } else {
+    c[3] = 0.5 - r / 3.0;
+    c[2] = r;
+    c[1] = -0.5 - r;
+    c[0] = r / 3.0;
+  }
+}
 
 // Weights of L along one direction at offsets -2..2 (w[0] is offset -2): the 3-point
-// second difference with diffusion a, minus velocity b times the first difference of the
-// given form on the side the flow comes from, spacing d.  The reaction is added apart.
-__device__ inline void dir_stencil(double a, double b, double d, int points, double r,
-                                   double (&w)[5]) {
-  const double d2 = a / (d * d);
-  double c[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // first difference, backward side
-  if (points == 2) {
-    c[2] = 1.0 / d;
-    c[1] = -1.0 / d;
-  } else if (points == 3) {
-    c[2] = 3.0 / (2.0 * d);
-    c[1] = -4.0 / (2.0 * d);
-    c[0] = 1.0 / (2.0 * d);
-  } else {
-    c[3] = 1.0 / (2.0 * d) - r / (3.0 * d);
-    c[2] = r / d;
-    c[1] = -1.0 / (2.0 * d) - r / d;
-    c[0] = r / (3.0 * d);
-  }
+// second difference with diffusion a, minus velocity b times the first difference (unit
+// weights cu, on the side the flow comes from: the mirror image where b < 0), spacing
+// reciprocals id = 1/d and id2 = 1/d^2.  The reaction is added apart.
+__device__ inline void dir_stencil(double a, double b, const double (&cu)[5], double id,
+                                   double id2, double (&w)[5]) {
+  const double d2 = a * id2;
   const bool back = b >= 0.0;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    const double ck = back ? c[k] : -c[4 - k];  // forward side: the mirror image
+    const double ck = (back ? cu[k] : -cu[4 - k]) * id;
     const double dk = (k == 1 || k == 3) ? d2 : (k == 2 ? -2.0 * d2 : 0.0);
     w[k] = dk - b * ck;
   }
@@ -89,53 +97,9 @@ __device__ inline int fold(int j, int n, double d, double gm, double gp, double&
   return j;
 }
 
-// Banded elimination of one line of n rows (row i at offset i * sd of each plane): band
-// planes B[0..4] (offsets -2..2) and right-hand side Rh; the normalised upper factors and
-// right-hand sides are written over B[3], B[4], Rh; the solution goes to x.
-__device__ inline void band_line(double* B0, double* B1, double* B2, double* B3, double* B4,
-                                 double* Rh, double* x, int n, int sd) {
-  // row i (diagonal, +1, +2, rhs), row i + 1 (-1, 0, +1, +2, rhs), row i + 2 (all)
-  double a2 = B2[0], a3 = B3[0], a4 = B4[0], ar = Rh[0];
-  double b1 = 0.0, b2 = 1.0, b3 = 0.0, b4 = 0.0, br = 0.0;
-  double c0 = 0.0, c1 = 0.0, c2 = 1.0, c3 = 0.0, c4 = 0.0, cr = 0.0;
-  if (n > 1) b1 = B1[sd], b2 = B2[sd], b3 = B3[sd], b4 = B4[sd], br = Rh[sd];
-  if (n > 2) {
-    const int at = 2 * sd;
-    c0 = B0[at], c1 = B1[at], c2 = B2[at], c3 = B3[at], c4 = B4[at], cr = Rh[at];
-  }
-  for (int i = 0; i < n; ++i) {
-    const int at = i * sd;
-    const double inv = 1.0 / a2;
-    const double u1 = a3 * inv, u2 = a4 * inv, y = ar * inv;
-    B3[at] = u1;
-    B4[at] = u2;
-    Rh[at] = y;
-    // rows i + 1 and i + 2 lose their entries in column i
-    b2 = fma(-b1, u1, b2);
-    b3 = fma(-b1, u2, b3);
-    br = fma(-b1, y, br);
-    c1 = fma(-c0, u1, c1);
-    c2 = fma(-c0, u2, c2);
-    cr = fma(-c0, y, cr);
-    a2 = b2, a3 = b3, a4 = b4, ar = br;
-    b1 = c1, b2 = c2, b3 = c3, b4 = c4, br = cr;
-    if (i + 3 < n) {
-      const int nx = (i + 3) * sd;
-      c0 = B0[nx], c1 = B1[nx], c2 = B2[nx], c3 = B3[nx], c4 = B4[nx], cr = Rh[nx];
-    } else {
-      c0 = 0.0, c1 = 0.0, c2 = 1.0, c3 = 0.0, c4 = 0.0, cr = 0.0;
-    }
-  }
-  double x1 = 0.0, x2 = 0.0;  // x_{i+1}, x_{i+2}
-  for (int i = n - 1; i >= 0; --i) {
-    const int at = i * sd;
-    const double v = fma(-B4[at], x2, fma(-B3[at], x1, Rh[at]));
-    x[at] = v;
-    x2 = x1;
-    x1 = v;
-  }
-}
-
+// NC constant and NS time-dependent source terms (compile-time counts, so that the
+// source loads of a line's points carry no branches and issue together).
+template <int NC, int NS>
 __global__ __launch_bounds__(64) void k_burst_adi_hu(AduArgs A) {
   extern __shared__ __align__(16) double lds[];
   const int mx = A.g.m_xi, me = A.g.m_eta, M = A.g.M;
@@ -145,6 +109,9 @@ __global__ __launch_bounds__(64) void k_burst_adi_hu(AduArgs A) {
   const long long p0 = (long long)blockIdx.x * A.ppb;
   const bool live = slot < A.ppb && p0 + slot < A.g.P;
   const double dx = A.g.dxi, de = A.g.deta;
+  const double idx = 1.0 / dx, idx2 = 1.0 / (dx * dx), ide = 1.0 / de, ide2 = 1.0 / (de * de);
+  double cu[5];
+  d1_unit(A.points, A.r, cu);
   const double h = 0.5 * A.dt;
   const long long P = A.plane;
   const int npts = A.ppb * pm;
@@ -157,76 +124,96 @@ __global__ __launch_bounds__(64) void k_burst_adi_hu(AduArgs A) {
     if (p0 + sl < A.g.P) lds[sl * per + ADU_PLANES * pm + e] = A.edge[(p0 + sl) * 4 * M + e];
   }
   __syncthreads();
+  double* b = lds + (live ? slot : 0) * per;
+  double* U1 = b + 2 * pm;
+  double* U2 = b + 3 * pm;
+  double* Y = b + 4 * pm;
+  const double* eg = b + ADU_PLANES * pm;
   for (int s = 0; s < A.n_t; ++s) {
     const double th = A.t_n + s * A.dt + 0.5 * A.dt;
-    double T[2] = {0.0, 0.0};
+    double T[NS > 0 ? NS : 1] = {0.0};
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (j < A.src.ns) T[j] = time_factor(A.src, j, th);
+    for (int j = 0; j < NS; ++j) T[j] = time_factor(A.src, j, th);
     for (int half = 0; half < 2; ++half) {
-      for (int q = threadIdx.x; q < npts; q += 64) {
-        const int sl = q / pm, at = q - sl * pm;
-        if (p0 + sl >= A.g.P) continue;
-        double* b = lds + sl * per;
-        const double* src = half == 0 ? b : b + pm;  // u^n, then u*
-        const double* eg = b + ADU_PLANES * pm;
-        const double* Cs = A.coef + (p0 + sl) * pm;
-        const int l = at / mx, k = at - l * mx;
-        const double al = Cs[at], ga = Cs[P + at], nu = Cs[2 * P + at], om = Cs[3 * P + at],
-                     ph = Cs[4 * P + at];
-        double sv = 0.0;
-        for (int c = 0; c < A.src.nconst; ++c) sv += A.src.ca[c] * Cs[A.src.plane_c[c] * P + at];
+      const bool rows = half == 0;
+      const int n = rows ? mx : me, nc = rows ? me : mx;  // points along and across
+      if (live && lane < nc) {
+        const double* src = b + half * pm;  // u^n, then u*
+        double* dst = b + (1 - half) * pm;
+        const double* Cs = A.coef + (p0 + slot) * pm;
+        const int si = rows ? 1 : mx, sc = rows ? mx : 1;
+        const int base = rows ? lane * mx : lane;  // the line's first point
+        const double di = rows ? dx : de, dc = rows ? de : dx;
+        const double i_id = rows ? idx : ide, i_id2 = rows ? idx2 : ide2;
+        const double c_id = rows ? ide : idx, c_id2 = rows ? ide2 : idx2;
+        const double gim = rows ? eg[lane] : eg[2 * M + lane];
+        const double gip = rows ? eg[M + lane] : eg[3 * M + lane];
+        // rows i - 1 and i - 2, normalised: upper factors and right-hand side
+        double p1 = 0.0, p2 = 0.0, py = 0.0, q1 = 0.0, q2 = 0.0, qy = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < n; ++i) {
+          const int at = base + i * si;
+          const double al = Cs[at], ga = Cs[P + at], nu = Cs[2 * P + at], om = Cs[3 * P + at],
+                       ph = Cs[4 * P + at];
+          double sv = 0.0;
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          if (j < A.src.ns) sv += T[j] * Cs[A.src.plane_t[j] * P + at];
-        // implicit weights along the line (xi in the first half), explicit across it
-        double wi[5], wc[5];
-        dir_stencil(half == 0 ? al : ga, half == 0 ? nu : om, half == 0 ? dx : de, A.points,
-                    A.r, wi);
-        dir_stencil(half == 0 ? ga : al, half == 0 ? om : nu, half == 0 ? de : dx, A.points,
-                    A.r, wc);
-        const int ni = half == 0 ? mx : me, nc = half == 0 ? me : mx;
-        const int ii = half == 0 ? k : l, ic = half == 0 ? l : k;
-        const int sc = half == 0 ? mx : 1;
-        const double di = half == 0 ? dx : de, dc = half == 0 ? de : dx;
-        // edge data: along the implicit line at this point's crossing index, and across
-        const double gim = half == 0 ? eg[l] : eg[2 * M + k];
-        const double gip = half == 0 ? eg[M + l] : eg[3 * M + k];
-        const double gcm = half == 0 ? eg[2 * M + k] : eg[l];
-        const double gcp = half == 0 ? eg[3 * M + k] : eg[M + l];
-        const int base_c = at - ic * sc;
-        double ex = 0.5 * ph * src[at];
+          for (int c = 0; c < NC; ++c) sv += A.src.ca[c] * Cs[A.src.plane_c[c] * P + at];
 #pragma unroll
-        for (int o = 0; o < 5; ++o) {
-          double cst;
-          const int j = fold(ic + o - 2, nc, dc, gcm, gcp, cst);
-          ex = fma(wc[o], src[base_c + j * sc] + cst, ex);
+          for (int j = 0; j < NS; ++j) sv += T[j] * Cs[A.src.plane_t[j] * P + at];
+          double wi[5], wc[5];  // along the line (implicit), across it (explicit)
+          dir_stencil(rows ? al : ga, rows ? nu : om, cu, i_id, i_id2, wi);
+          dir_stencil(rows ? ga : al, rows ? om : nu, cu, c_id, c_id2, wc);
+          // explicit part: the crossing line through point i, where this line sits at
+          // index `lane`, with that line's edge data for its ghosts
+          const double gcm = rows ? eg[2 * M + i] : eg[i];
+          const double gcp = rows ? eg[3 * M + i] : eg[M + i];
+          const int cbase = at - lane * sc;
+          double ex = 0.5 * ph * src[at];
+#pragma unroll
+          for (int o = 0; o < 5; ++o) {
+            double cst;
+            const int j = fold(lane + o - 2, nc, dc, gcm, gcp, cst);
+            ex = fma(wc[o], src[cbase + j * sc] + cst, ex);
+          }
+          double rhs = src[at] + h * ex + h * sv;
+          double band[5] = {0.0, 0.0, 1.0 - h * 0.5 * ph, 0.0, 0.0};
+#pragma unroll
+          for (int o = 0; o < 5; ++o) {
+            double cst;
+            const int t = fold(i + o - 2, n, di, gim, gip, cst) - i + 2;  // in 0..4
+#pragma unroll
+            for (int k = 0; k < 5; ++k) band[k] -= t == k ? h * wi[o] : 0.0;
+            rhs += h * wi[o] * cst;
+          }
+          // entries in columns i - 2 and i - 1 (zero in the first two rows, where the
+          // carried rows are zero too) against the rows above, then normalise
+          {
+            const double f = band[0];
+            band[1] = fma(-f, q1, band[1]);
+            band[2] = fma(-f, q2, band[2]);
+            rhs = fma(-f, qy, rhs);
+          }
+          {
+            const double f = band[1];
+            band[2] = fma(-f, p1, band[2]);
+            band[3] = fma(-f, p2, band[3]);
+            rhs = fma(-f, py, rhs);
+          }
+          const double inv = 1.0 / band[2];
+          q1 = p1, q2 = p2, qy = py;
+          p1 = band[3] * inv, p2 = band[4] * inv, py = rhs * inv;
+          U1[at] = p1;
+          U2[at] = p2;
+          Y[at] = py;
         }
-        double rhs = src[at] + h * ex + h * sv;
-        double band[5] = {0.0, 0.0, 1.0 - h * 0.5 * ph, 0.0, 0.0};
-#pragma unroll
-        for (int o = 0; o < 5; ++o) {
-          double cst;
-          const int t = fold(ii + o - 2, ni, di, gim, gip, cst) - ii + 2;  // in 0..4
-#pragma unroll
-          for (int q = 0; q < 5; ++q) band[q] -= t == q ? h * wi[o] : 0.0;
-          rhs += h * wi[o] * cst;
-        }
-#pragma unroll
-        for (int o = 0; o < 5; ++o) b[(2 + o) * pm + at] = band[o];
-        b[7 * pm + at] = rhs;
-      }
-      __syncthreads();
-      if (live) {
-        double* b = lds + slot * per;
-        if (half == 0 && lane < me) {
-          const int o = lane * mx;
-          band_line(b + 2 * pm + o, b + 3 * pm + o, b + 4 * pm + o, b + 5 * pm + o,
-                    b + 6 * pm + o, b + 7 * pm + o, b + pm + o, mx, 1);
-        } else if (half == 1 && lane < mx) {
-          const int o = lane;
-          band_line(b + 2 * pm + o, b + 3 * pm + o, b + 4 * pm + o, b + 5 * pm + o,
-                    b + 6 * pm + o, b + 7 * pm + o, b + o, me, mx);
+        double x1 = 0.0, x2 = 0.0;  // x_{i+1}, x_{i+2}
+#pragma unroll 4
+        for (int i = n - 1; i >= 0; --i) {
+          const int at = base + i * si;
+          const double v = fma(-U2[at], x2, fma(-U1[at], x1, Y[at]));
+          dst[at] = v;
+          x2 = x1;
+          x1 = v;
         }
       }
       __syncthreads();
@@ -275,7 +262,17 @@ hipError_t launch_burst_adi_hu(const Geo& g, const SrcInfo& src, const double* c
   adu_shape(g.m_xi, g.m_eta, a.ppb, lds);
   if (a.ppb < 1) return hipErrorInvalidValue;
   const dim3 grid((g.P + a.ppb - 1) / a.ppb);
-  hipLaunchKernelGGL(k_burst_adi_hu, grid, dim3(64), lds, s, a);
+  if (src.nconst < 0 || src.nconst > PD_MAXTERM || src.ns < 0 || src.ns > 2)
+    return hipErrorInvalidValue;
+  static_assert(PD_MAXTERM == 4, "one instance per constant-term count");
+  using K = void (*)(AduArgs);
+  static const K tab[5][3] = {
+      {k_burst_adi_hu<0, 0>, k_burst_adi_hu<0, 1>, k_burst_adi_hu<0, 2>},
+      {k_burst_adi_hu<1, 0>, k_burst_adi_hu<1, 1>, k_burst_adi_hu<1, 2>},
+      {k_burst_adi_hu<2, 0>, k_burst_adi_hu<2, 1>, k_burst_adi_hu<2, 2>},
+      {k_burst_adi_hu<3, 0>, k_burst_adi_hu<3, 1>, k_burst_adi_hu<3, 2>},
+      {k_burst_adi_hu<4, 0>, k_burst_adi_hu<4, 1>, k_burst_adi_hu<4, 2>}};
+  hipLaunchKernelGGL(tab[src.nconst][src.ns], grid, dim3(64), lds, s, a);
   return hipGetLastError();
 }
 

@@ -696,7 +696,7 @@ pd_status pd_micro_burst_adi_upwind(pd_grid g, double* state, const double* edge
     adu_shape(g->g.m_xi, g->g.m_eta, ppb, lds);
     if (ppb < 1)
       return fail(PD_EINVAL,
-                  "the ADI upwind burst needs 8 m_xi m_eta + 4 max(m_xi, m_eta) <= 8192");
+                  "the ADI upwind burst needs 5 m_xi m_eta + 4 max(m_xi, m_eta) <= 8192");
   }
   HIPCHK(hipSetDevice(g->d.device));
   HIPCHK(launch_burst_adi_hu(g->g, g->src, g->coef(),

@@ -41,7 +41,8 @@ CASES = {
     "tanh": (lambda: W.config2(n=7, m=9), 30.0, 2),
     "annulus": (lambda: W.config3(n_r=6, n_theta=8, m=9), 20.0, 2),
     "sec412": (lambda: W.paper_cdr(2, lam=0.1, n=6, m=11), None, 2),
-    "m31": (lambda: W.config2(n=5, m=31), 20.0, 2),  # largest square patch (one per wave)
+    "m31": (lambda: W.config2(n=5, m=31), 20.0, 2),  # two lines of 31 fill a wave
+    "m40": (lambda: W.config2(n=4, m=40), 20.0, 2),  # largest square patch in 64 KiB
     "ragged_13x7": (lambda: ragged("central", 13, 7), 20.0, 3),
     "ragged_5x12": (lambda: ragged("upwind", 5, 12, "tanh", 1.5), 20.0, 2),
     "m3": (lambda: W.paper_cdr(2, lam=0.1, n=6, m=3), None, 2),
@@ -133,9 +134,9 @@ def test_adi_upwind_rejects_bad_arguments(pd):
         with pytest.raises(pd.PdError) as e:
             g.micro_burst_adi_upwind(state, edge, 0.0, dt, n, points, r)
         assert e.value.status == -1
-    big = pd.Grid(W.config2(n=5, m=32))  # 8 * 32^2 + 4 * 32 doubles exceed 64 KiB of LDS
-    s2 = torch.zeros((big.P, 32, 32), dtype=torch.float64, device="cuda")
-    e2 = torch.zeros((big.P, 4, 32), dtype=torch.float64, device="cuda")
+    big = pd.Grid(W.config2(n=4, m=41))  # 5 * 41^2 + 4 * 41 doubles exceed 64 KiB of LDS
+    s2 = torch.zeros((big.P, 41, 41), dtype=torch.float64, device="cuda")
+    e2 = torch.zeros((big.P, 4, 41), dtype=torch.float64, device="cuda")
     with pytest.raises(pd.PdError) as e:
         big.micro_burst_adi_upwind(s2, e2, 0.0, 1e-7, 2, 3, 0.5)
     assert e.value.status == -1 and "8192" in str(e.value)

@@ -414,6 +414,9 @@ __device__ __forceinline__ float from_bf16(unsigned short h) {
 }
 
 constexpr int K1P = CL_K1P;
+// LDS row strides (bfloat16 entries) of the input and hidden tiles, padded by four so that
+// the 32 rows one MFMA operand read spans fall on different banks.
+constexpr int XS = K1P + 4, HS = CL_HID + 4;
 
 // Packed bfloat16 weights: W1t [CL_HID][K1P] and W2t [CL_HID][CL_HID] (output-major, the
 // reduction index contiguous), w3 [CL_HID].
@@ -432,8 +435,8 @@ __global__ void k_pack(const float* __restrict__ par, unsigned short* __restrict
 }
 
 
-// The network on a tile of 64 rows.  xt: LDS [64][K1P] bfloat16 inputs; ht: LDS [64][CL_HID]
-// bfloat16 scratch; part: LDS [2][64] floats; out: LDS [64] floats (results).  256 threads:
+// The network on a tile of 64 rows.  xt: LDS [64][XS] bfloat16 inputs (K1P used); ht: LDS
+// [64][HS] bfloat16 scratch (CL_HID used); part: LDS [2][64] floats; out: LDS [64] floats (results).  256 threads:
 // wave w computes rows 32 (w & 1) .. + 31 and columns 64 (w >> 1) .. + 63 of each layer with
 // 32x32x8 MFMA tiles; lane l holds A(row l % 32, k 4 (l / 32) .. + 3), B(k 4 (l / 32) .. + 3,
 // col l % 32) and accumulator entry e at row 8 (e / 4) + 4 (l / 32) + e % 4, col l % 32.
@@ -448,7 +451,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW& W, const unsigned short* xt
   for (int t = 0; t < 2; ++t) acc[t] = f32x16{};
 #pragma unroll
   for (int ks = 0; ks < K1P / 8; ++ks) {
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(xt + (32 * mt + li) * K1P + 8 * ks + lk);
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(xt + (32 * mt + li) * XS + 8 * ks + lk);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int n = 64 * nh + 32 * t + li;
@@ -463,7 +466,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW& W, const unsigned short* xt
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       const int row = 32 * mt + 8 * (e / 4) + (lane >> 5) * 4 + (e & 3);
-      ht[row * CL_HID + col] = to_bf16(gelu_infer(acc[t][e] + bias));
+      ht[row * HS + col] = to_bf16(gelu_infer(acc[t][e] + bias));
     }
   }
   __syncthreads();
@@ -472,7 +475,7 @@ __device__ __forceinline__ void mlp_tile(const MlpW& W, const unsigned short* xt
   for (int t = 0; t < 2; ++t) acc[t] = f32x16{};
 #pragma unroll 4
   for (int ks = 0; ks < CL_HID / 8; ++ks) {
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(ht + (32 * mt + li) * CL_HID + 8 * ks + lk);
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(ht + (32 * mt + li) * HS + 8 * ks + lk);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int n = 64 * nh + 32 * t + li;
@@ -513,14 +516,14 @@ __device__ __forceinline__ void mlp_tile(const MlpW& W, const unsigned short* xt
 // Network outputs for standardised rows Xn [n][33] (64 rows per block).
 __global__ __launch_bounds__(256) void k_mlp_infer(long long n, const float* __restrict__ Xn,
                                                    MlpW W, float* __restrict__ out) {
-  __shared__ __align__(16) unsigned short xt[64 * K1P];
-  __shared__ __align__(16) unsigned short ht[64 * CL_HID];
+  __shared__ __align__(16) unsigned short xt[64 * XS];
+  __shared__ __align__(16) unsigned short ht[64 * HS];
   __shared__ float part[128], res[64];
   const long long r0 = (long long)blockIdx.x * 64;
   for (int e = threadIdx.x; e < 64 * K1P; e += 256) {
     const int r = e / K1P, k = e - r * K1P;
     const long long gr = r0 + r;
-    xt[e] = (k < CL_FEAT && gr < n) ? to_bf16(Xn[gr * CL_FEAT + k]) : (unsigned short)0;
+    xt[r * XS + k] = (k < CL_FEAT && gr < n) ? to_bf16(Xn[gr * CL_FEAT + k]) : (unsigned short)0;
   }
   __syncthreads();
   mlp_tile(W, xt, ht, part, res);
@@ -538,8 +541,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(long long n, const float* __r
 // runs the network on its four 64-row tiles (MFMA), and each wave writes its patches'
 // projected values.
 __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
-  __shared__ __align__(16) unsigned short xt[4 * 64 * K1P];
-  __shared__ __align__(16) unsigned short ht[64 * CL_HID];
+  __shared__ __align__(16) unsigned short xt[4 * 64 * XS];
+  __shared__ __align__(16) unsigned short ht[64 * HS];
   __shared__ float part[128], res[4 * 64];
   __shared__ double sF0[4 * 64], sS[4 * 64], sU[4 * 64];
   __shared__ int sNode[4 * 64];
@@ -572,7 +575,7 @@ __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
   const int r = w * 64 + lane;
   const long long p = p0 + lane;
   const bool mine = valid && p < A.g.P;
-  unsigned short* xr = xt + r * K1P;
+  unsigned short* xr = xt + r * XS;
   if (mine) {
     Feat f;
     closure_features(A.g, A.src, st + p * CL_NST, Uin, t_n, f);
@@ -589,7 +592,7 @@ __global__ __launch_bounds__(256) void k_closure_step(ClosureArgs Cl) {
   __syncthreads();
   for (int tile = 0; tile < 4; ++tile)  // uniform: tiles of units past the end are skipped
     if (blockIdx.x * 4 + tile < Cl.n_items)
-      mlp_tile(Cl.W, xt + tile * 64 * K1P, ht, part, res + tile * 64);
+      mlp_tile(Cl.W, xt + tile * 64 * XS, ht, part, res + tile * 64);
   if (mine) {
     const double Fh = sF0[r] + sS[r] * ((double)Cl.ys[0] + (double)Cl.ys[1] * (double)res[r]);
     const double un = sU[r] + A.dt_macro * Fh;

@@ -160,13 +160,14 @@ __global__ __launch_bounds__(HU_THREADS) void k_burst_hu(HuArgs A) {
     a = fma(w[i][8], c[2 * W], a);
     return a;
   };
+  // the point's value and the ghost copies it determines (offsets 0: none)
   auto put = [&](int i, double* t, double v) {
     double* c = t + off[i];
     c[0] = v;
-    c[gx[i][0]] = v;
-    c[ge[i][0]] = v;
-    if (mx < 6) c[gx[i][1]] = v;
-    if (me < 6) c[ge[i][1]] = v;
+    if (gx[i][0]) c[gx[i][0]] = v;
+    if (ge[i][0]) c[ge[i][0]] = v;
+    if (gx[i][1]) c[gx[i][1]] = v;
+    if (ge[i][1]) c[ge[i][1]] = v;
   };
   __syncthreads();
   // K0 = dt L_h(u(0)) from the lifted tile with its edge-data ghosts, then v = 0

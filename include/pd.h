@@ -139,6 +139,7 @@ typedef struct {
                              /* 3: DPP inside each wave, band edges through LDS        */
   int32_t tuned;             /* 1 once pd_autotune chose the launch shape               */
   double tuned_ms;           /* its measured time per fused step (ms), else 0           */
+  int32_t resident_solve;    /* 1 if the last pd_solve ran resident launches           */
 } pd_info;
 
 typedef struct pd_grid_s* pd_grid;
@@ -279,13 +280,18 @@ pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
 /* Options: PD_OPT_ALLOW_UNSTABLE (0/1) skips the stability guard; PD_OPT_ROWS_PER_LANE,
  * PD_OPT_COLS_PER_LANE (1..4), PD_OPT_PATCHES_PER_BLOCK, PD_OPT_BLOCK_THREADS (upper bound,
  * 64..256) and PD_OPT_EXCHANGE (1 LDS, 2 in-wave, 3 hybrid) set the fused burst's launch shape
- * (0 = automatic).  Results do not depend on the launch shape (bitwise). */
+ * (0 = automatic).  Results do not depend on the launch shape (bitwise).
+ * PD_OPT_RESIDENT_SOLVE (default 1): pd_solve runs each replay of its in-wave FP64 steps
+ * as one launch whose waves stay resident across the steps (when they all fit on the
+ * device at once and a patch block has at most 7 patches), else one launch per step;
+ * the results are bitwise the same. */
 #define PD_OPT_ALLOW_UNSTABLE 1
 #define PD_OPT_ROWS_PER_LANE 2
 #define PD_OPT_PATCHES_PER_BLOCK 3
 #define PD_OPT_BLOCK_THREADS 4
 #define PD_OPT_COLS_PER_LANE 5
 #define PD_OPT_EXCHANGE 6
+#define PD_OPT_RESIDENT_SOLVE 7
 pd_status pd_set_option(pd_grid g, int32_t option, int64_t value);
 
 /* Launch-shape autotuner of the fused step (not in the paper: a property of this library).

@@ -19,7 +19,7 @@ ARCH = os.environ.get("PD_OFFLOAD_ARCH", "gfx950")
 BURSTS = [f"pd_burst_{fam}{mode}_{prec}.hip" for fam in ("lds", "x", "h") for mode in ("", "s")
           for prec in ("f64", "f32")]
 SOURCES = ["pd_host.hip", "pd_coeff.hip", "pd_split.hip", *BURSTS, "pd_batch.hip",
-           "pd_closure.hip", "pd_fd.hip", "pd_adi.hip", "pd_adi_upwind.hip",
+           "pd_closure.hip", "pd_fd.hip", "pd_adi.hip", "pd_adi_upwind.hip", "pd_solve_x_f64.hip",
            "pd_upwind.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

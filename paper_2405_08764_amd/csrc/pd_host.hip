@@ -35,6 +35,13 @@ PD_DECL(hs_f64)
 PD_DECL(hs_f32)
 #undef PD_DECL
 
+// Resident fused solve with the in-wave exchange (pd_solve_x_f64.hip).
+size_t solve_x_extra_lds(int ppb, int mx, int me, int nconst);
+hipError_t launch_zero_flags(long long* f, int n, hipStream_t s);
+hipError_t launch_solve_x_f64(int R, int C, const BurstArgs& a, long long* flags, int* err,
+                              int steps, const double* ttab0, const double* bval0, int per,
+                              int blocks, size_t lds, hipStream_t s, int* resident);
+
 // ADI burst with the higher-order upwind differences (pd_adi_upwind.hip): patches per
 // wave and LDS bytes for m_xi x m_eta patches (ppb = 0 when none fits), and the launcher.
 void adu_shape(int mx, int me, int& ppb, size_t& lds);
@@ -136,7 +143,7 @@ struct pd_grid_s {
   size_t ws_bytes = 0;
   size_t off_coef = 0, off_pmap = 0, off_tab = 0, off_desc = 0, off_V = 0, off_flag = 0,
          off_clock = 0, off_part = 0, off_lim = 0, off_ttab = 0, off_bval = 0, off_cst = 0,
-         need = 0;
+         off_pflag = 0, need = 0;
   bool cst_ok = false;  // static closure data computed for the current coefficients
   // coefficients
   bool coeffs_set = false;
@@ -147,6 +154,7 @@ struct pd_grid_s {
   double lim_micro = 0.0, lim_macro = 0.0;
   // options
   int allow_unstable = 0, opt_R = 0, opt_C = 0, opt_ppb = 0, opt_threads = 0, opt_xch = 0;
+  int opt_resident = 1, last_resident = 0;
   // launch shape of the burst, fused and split mode alike
   int R = 0, C = 0, xch = 0, ppb = 0, threads = 0, blocks = 0;
   size_t lds = 0;
@@ -159,7 +167,7 @@ struct pd_grid_s {
   double g_dtm = 0, g_dt = 0;
   int g_nt = 0;
   double* g_U = nullptr;
-  int g_R = 0, g_C = 0, g_ppb = 0, g_threads = 0, g_xch = 0;
+  int g_R = 0, g_C = 0, g_ppb = 0, g_threads = 0, g_xch = 0, g_res = 0;
   // autotuner result
   int tuned = 0;
   double tuned_ms = 0.0;
@@ -177,6 +185,7 @@ struct pd_grid_s {
   double* V() { return reinterpret_cast<double*>(ws + off_V); }
   int* flag() { return reinterpret_cast<int*>(ws + off_flag); }
   Clock* clock() { return reinterpret_cast<Clock*>(ws + off_clock); }
+  long long* pflags() { return reinterpret_cast<long long*>(ws + off_pflag); }
   double* part() { return reinterpret_cast<double*>(ws + off_part); }
   double* lim() { return reinterpret_cast<double*>(ws + off_lim); }
   double* ttab() { return reinterpret_cast<double*>(ws + off_ttab); }
@@ -511,6 +520,7 @@ pd_status pd_create_grid(const pd_grid_desc* d, pd_grid* out) {
   g->off_ttab = o; o = align256(o + TT_CAP * sizeof(double));
   g->off_bval = o; o = align256(o + (size_t)MAX_REPLAY * boundary_count(G) * sizeof(double));
   g->off_cst = o; o = align256(o + (size_t)G.P * CL_NST * sizeof(double));
+  g->off_pflag = o; o = align256(o + (size_t)G.P * sizeof(long long));
   g->need = o;
   choose_shape(g);
   *out = g;
@@ -550,6 +560,7 @@ pd_status pd_query(pd_grid g, pd_info* out) {
   I.block_threads = g->threads;
   out->tuned = g->tuned;
   out->tuned_ms = g->tuned_ms;
+  out->resident_solve = g->last_resident;
   return PD_OK;
 }
 
@@ -855,18 +866,36 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
   const int reps = n_steps / S, rem = n_steps - reps * S;
   const int nb = boundary_count(g->g);
   a.nb = nb;
+  // resident solve: in-wave FP64 steps, every wave's neighbour list within one wave
+  const bool res = g->opt_resident && g->xch == XCH_LANES && g->d.precision == PD_F64 &&
+                   g->threads == 64 && 9 * g->ppb <= 64;
   const bool reuse = g->gexec && g->g_steps == S && g->g_dtm == dt_macro && g->g_dt == dt &&
                      g->g_nt == n_t && g->g_U == U && g->g_R == g->R && g->g_C == g->C &&
-                     g->g_ppb == g->ppb && g->g_threads == g->threads && g->g_xch == g->xch;
+                     g->g_ppb == g->ppb && g->g_threads == g->threads && g->g_xch == g->xch &&
+                     g->g_res == (int)res;
   if (own) {
     HIPCHK(hipEventRecord(g->ev_in, s));
     HIPCHK(hipStreamWaitEvent(w, g->ev_in, 0));
   }
   g->tt_ok = false;  // k_replay rewrites the time-factor table
   HIPCHK(launch_clock_init(g->clock(), t0, dt_macro, U, g->V(), w));
+  if (res) HIPCHK(launch_zero_flags(g->pflags(), g->blocks, w));
+  g->last_resident = 0;
   auto steps = [&](int count) -> hipError_t {
     hipError_t e = launch_replay(g->g, g->src, g->ddesc(), g->clock(), count, n_t, dt,
                                  g->ttab(), g->bvals(), w);
+    if (res && e == hipSuccess) {
+      int resident = 0;
+      a.k = 0;
+      a.ttab = g->ttab();
+      a.bvals = nullptr;  // written by the owning waves step by step
+      e = launch_solve_x_f64(g->R, g->C, a, g->pflags(), g->flag() + 1, count, g->ttab(),
+                             g->bvals(), (int)per, g->blocks,
+                             g->lds + solve_x_extra_lds(g->ppb, g->g.m_xi, g->g.m_eta, g->src.nconst), w,
+                             &resident);
+      g->last_resident = resident;
+      if (e != hipSuccess || resident) return e;
+    }
     for (int k = 0; k < count && e == hipSuccess; ++k) {
       a.k = k;
       a.ttab = g->ttab() + k * per;
@@ -898,6 +927,7 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     g->g_ppb = g->ppb;
     g->g_threads = g->threads;
     g->g_xch = g->xch;
+    g->g_res = (int)res;
   }
   for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(g->gexec, w));
   if (rem) HIPCHK(steps(rem));
@@ -1008,9 +1038,13 @@ pd_status pd_sync(pd_grid g, void* stream) {
   if (st) return st;
   HIPCHK(hipSetDevice(g->d.device));
   HIPCHK(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
-  int flag = 0;
-  HIPCHK(hipMemcpy(&flag, g->flag(), sizeof(int), hipMemcpyDeviceToHost));
-  if (flag) {
+  int flag[2] = {0, 0};
+  HIPCHK(hipMemcpy(flag, g->flag(), 2 * sizeof(int), hipMemcpyDeviceToHost));
+  if (flag[1]) {
+    HIPCHK(hipMemset(g->flag(), 0, 2 * sizeof(int)));
+    return fail(PD_EDEVICE, "a resident solve's wait for neighbouring waves gave up");
+  }
+  if (flag[0]) {
     HIPCHK(hipMemset(g->flag(), 0, sizeof(int)));
     return fail(PD_ENONFINITE, "a kernel produced a non-finite value");
   }
@@ -1046,6 +1080,7 @@ pd_status pd_set_option(pd_grid g, int32_t option, int64_t value) {
   if (!g) return fail(PD_EINVAL, "null grid");
   switch (option) {
     case PD_OPT_ALLOW_UNSTABLE: g->allow_unstable = value ? 1 : 0; return PD_OK;
+    case PD_OPT_RESIDENT_SOLVE: g->opt_resident = value ? 1 : 0; return PD_OK;
     case PD_OPT_ROWS_PER_LANE:
       if (value < 0 || value > 11) return fail(PD_EINVAL, "unsupported rows per lane");
       g->opt_R = (int)value;

@@ -22,7 +22,7 @@ PREC = {"f64": 0, "f32": 1}
 FN = {"sin": 0, "cos": 1, "exp": 2, "poly": 3}
 TF = {"const": 0, "exp": 1, "sin": 2}
 OPT_ALLOW_UNSTABLE, OPT_ROWS_PER_LANE, OPT_PATCHES_PER_BLOCK, OPT_BLOCK_THREADS = 1, 2, 3, 4
-OPT_COLS_PER_LANE, OPT_EXCHANGE = 5, 6
+OPT_COLS_PER_LANE, OPT_EXCHANGE, OPT_RESIDENT_SOLVE = 5, 6, 7
 TUNE_FORCE = 1
 
 STATUS = {0: "PD_OK", -1: "PD_EINVAL", -2: "PD_ESTATE", -3: "PD_EUNSTABLE", -4: "PD_EDEVICE",
@@ -83,7 +83,8 @@ class Info(C.Structure):
                 ("n_time_sources", C.c_int32), ("rows_per_lane", C.c_int32),
                 ("patches_per_block", C.c_int32), ("block_threads", C.c_int32),
                 ("cols_per_lane", C.c_int32), ("exchange", C.c_int32),
-                ("tuned", C.c_int32), ("tuned_ms", C.c_double)]
+                ("tuned", C.c_int32), ("tuned_ms", C.c_double),
+                ("resident_solve", C.c_int32)]
 
 
 class BatchMember(C.Structure):

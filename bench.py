@@ -53,6 +53,8 @@ FD_SOURCES = ["pd_fd.hip", "pd_internal.h"]
 HU_SOURCES = ["pd_upwind.hip", "pd_internal.h"]
 ADI_SOURCES = ["pd_adi.hip", "pd_internal.h"]
 ADU_SOURCES = ["pd_adi_upwind.hip", "pd_internal.h"]
+SOLVE_SOURCES = ["pd_solve_x_f64.hip", "pd_burst.inc", "pd_internal.h"]
+RESIDENT_STEPS = 16  # macro steps per graph replay, so per resident launch
 
 
 def burst_source_hash(files=None):
@@ -1263,7 +1265,8 @@ def main():
         kern = args.counter_kernel
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
-                 "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES}.get(kern)
+                 "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES,
+                 "k_solve_x": SOLVE_SOURCES}.get(kern)
         counter_summary(args.counter_summary, args.counter_match or
                         kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                         args.counter_last, counter_file(kern, args.workload, args.precision),
@@ -1273,7 +1276,8 @@ def main():
         kern = args.counter_kernel
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
-                 "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES}.get(kern)
+                 "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES,
+                 "k_solve_x": SOLVE_SOURCES}.get(kern)
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.counter_match or
                     kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                     args.calibrate_copy or 256, traffic_file(kern, args.workload, args.precision),
@@ -1349,18 +1353,30 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - s
         g.sync()
-        # Dominant kernel: the fused burst (pd_patch_step launches exactly that kernel),
-        # timed with HIP events on the stream it runs on.
-        V = torch.empty_like(U)
+        info = g.query()
+        resident = bool(info.resident_solve)
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                for _ in range(args.kernel_reps)]
-        for k, (a, b) in enumerate(evs):
-            a.record(stream)
-            g.patch_step(U if k % 2 == 0 else V, t["t0"], out=V if k % 2 == 0 else U)
-            b.record(stream)
-        torch.cuda.synchronize()
-        kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
-        info = g.query()
+        if resident:
+            # Dominant kernel: the resident solve, one launch per 16-step replay (with its
+            # table fill), timed with HIP events on the stream it runs on, per macro step.
+            for a, b in evs:
+                a.record(stream)
+                g.solve(U, n_steps=RESIDENT_STEPS)
+                b.record(stream)
+            torch.cuda.synchronize()
+            kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3 / RESIDENT_STEPS
+        else:
+            # Dominant kernel: the fused burst (pd_patch_step launches exactly that kernel),
+            # timed with HIP events on the stream it runs on.
+            V = torch.empty_like(U)
+            for k, (a, b) in enumerate(evs):
+                a.record(stream)
+                g.patch_step(U if k % 2 == 0 else V, t["t0"], out=V if k % 2 == 0 else U)
+                b.record(stream)
+            torch.cuda.synchronize()
+            kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+        g.sync()
         if args.calibrate_copy:
             # A plain streaming kernel of known traffic: read MIB MiB, write MIB MiB
             # (torch's vectorized elementwise multiply by one).
@@ -1389,7 +1405,19 @@ def main():
     peak = PEAK[args.precision]
     value = per_step * args.steps / el
     shape = f"{info.exchange},{info.cols_per_lane},{info.rows_per_lane},{info.patches_per_block}"
-    traffic = read_traffic(KERNEL_NAME[info.exchange], args.workload, args.precision, shape)
+    kname = "k_solve_x" if resident else KERNEL_NAME[info.exchange]
+    kfiles = SOLVE_SOURCES if resident else None
+    # per launch: the resident solve covers RESIDENT_STEPS macro steps; its coefficient
+    # planes are read once per launch, dt phi (and constant sources) once per step
+    per_launch = RESIDENT_STEPS if resident else 1
+    if resident:
+        n_const = sum(1 for (tf, _, _) in prob["src"] if tf[0] == "const")
+        alg_bytes = ((5 + n_src) * info.n_points * 8 / per_launch
+                     + (1 + (1 if n_const else 0)) * info.n_points * 8
+                     + info.n_xi * info.n_eta * 8 + info.n_patches * 8)
+    traffic = read_traffic(kname, args.workload, args.precision, shape, kfiles)
+    if traffic is not None:
+        traffic /= per_launch  # per macro step, like kernel_ms
     out = {
         "metric": "patch-point updates/s (and macro steps/s) of the plain GPU scheme",
         "value": value,
@@ -1418,13 +1446,15 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "algorithmic_bytes": alg_bytes,
-                     "kernel": KERNEL_NAME[info.exchange] + " (fused macro step)",
+                     "kernel": ("k_solve_x (resident fused solve, 16 macro steps per launch;"
+                                " per macro step)") if resident else
+                               KERNEL_NAME[info.exchange] + " (fused macro step)",
                      "kernel_ms": kern_s * 1e3,
                      "flops_per_update": flops_per_update,
                      "issued_flops_per_update": issued_flops_per_update,
                      "issued_frac": issued_flops_per_update * per_step / kern_s / peak,
-                     "counters": read_counters(KERNEL_NAME[info.exchange], args.workload,
-                                               args.precision, shape, kern_s)},
+                     "counters": read_counters(kname, args.workload, args.precision, shape,
+                                               kern_s * per_launch, kfiles)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, steps_cap=1000)

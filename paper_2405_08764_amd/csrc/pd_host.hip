@@ -168,6 +168,7 @@ struct pd_grid_s {
   int g_nt = 0;
   double* g_U = nullptr;
   int g_R = 0, g_C = 0, g_ppb = 0, g_threads = 0, g_xch = 0, g_res = 0;
+  int g_res_ran = 0;  // the captured replay launches the resident solve
   // autotuner result
   int tuned = 0;
   double tuned_ms = 0.0;
@@ -928,7 +929,9 @@ pd_status pd_solve(pd_grid g, double* U, double t0, double dt_macro, int32_t n_s
     g->g_threads = g->threads;
     g->g_xch = g->xch;
     g->g_res = (int)res;
+    g->g_res_ran = g->last_resident;
   }
+  if (reps > 0) g->last_resident = g->g_res_ran;
   for (int r = 0; r < reps; ++r) HIPCHK(hipGraphLaunch(g->gexec, w));
   if (rem) HIPCHK(steps(rem));
   if (n_steps & 1)

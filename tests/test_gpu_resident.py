@@ -82,3 +82,21 @@ def test_resident_solve_full_config2(pd):
     b = solve(pd, prob, False, 48, (2, 6))
     say("config2 max |diff|", float(np.max(np.abs(a - b))))
     assert np.array_equal(a, b)
+
+
+def test_resident_path_reported_on_graph_reuse(pd):
+    """A second solve of whole replays reuses the captured graph; the grid still reports the
+    resident path, and the two paths still agree."""
+    prob = W.config2(n=11, m=17)
+    out = []
+    for resident in (1, 0):
+        g = pd.Grid(prob)
+        g.set_option(pd.OPT_EXCHANGE, 2)
+        g.set_option(pd.OPT_RESIDENT_SOLVE, resident)
+        U = g.initial()
+        g.solve(U, n_steps=32)
+        g.solve(U, n_steps=32, t0=prob["time"]["t0"] + 32 * prob["time"]["dt_macro"])
+        g.sync()
+        assert g.query().resident_solve == resident
+        out.append(U.cpu().numpy())
+    assert np.array_equal(out[0], out[1])

@@ -171,13 +171,15 @@ def short_kernel_name(name):
 
 def stats_summary(csv_path, out, title, command, top=20, keep=""):
     """A rocprofv3 --stats kernel table (kernel_stats.csv) as a short text summary: the
-    `top` kernels by total time, and every kernel whose name contains `keep`."""
+    `top` kernels by total time, and every kernel whose name contains one of the
+    '|'-separated names in `keep`."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     for r in rows:
         r["Name"] = short_kernel_name(r["Name"])
-    rows = [r for k, r in enumerate(rows) if k < top or (keep and keep in r["Name"])]
+    keys = [k for k in keep.split("|") if k]
+    rows = [r for k, r in enumerate(rows) if k < top or any(x in r["Name"] for x in keys)]
     with open(out, "w") as fh:
         for line in title.strip().splitlines():
             fh.write(f"# {line}\n")
@@ -409,6 +411,22 @@ def make_batch(n_instances, n_steps, shapes_path=None, log=None):
 def reset_fields(grids, B):
     for g, U in zip(grids, B.U):
         g.initial(U=U)
+
+
+def time_launches(stream, launch, reps):
+    """Average seconds per call of `launch`: one untimed call, then `reps` calls back to
+    back between one pair of HIP events recorded on the stream they run on.  (An event pair
+    around every call adds the event packets' own processing to each launch: 10-50 us
+    on a 40-200 us kernel, against rocprofv3's kernel trace.)"""
+    import torch
+    launch()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        launch()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps / 1e3
 
 
 def time_batch(B, grids, warmup, steps, stream, closure=False):
@@ -736,14 +754,9 @@ def bench_refresh(args):
         # the dominant kernel: one sub-burst (split-mode burst), timed with HIP events
         state, edge = g.lift_bc(U)
         n_sub = t["n_t"] // Q
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.kernel_reps)]
-        for a, b in evs:
-            a.record(stream)
-            g.micro_burst(state, edge, t["t0"], t["dt_micro"], n_sub)
-            b.record(stream)
-        torch.cuda.synchronize()
-        kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+        kern_s = time_launches(
+            stream, lambda: g.micro_burst(state, edge, t["t0"], t["dt_micro"], n_sub),
+            args.kernel_reps)
         info = g.query()
         if args.calibrate_copy:
             calibration_copy(args.calibrate_copy)
@@ -858,14 +871,7 @@ def bench_adi(args):
         el = time.perf_counter() - s0
         g.sync()
         state, edge = g.lift_bc(U)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.kernel_reps)]
-        for a, b in evs:
-            a.record(stream)
-            burst(state, edge, 0.0)
-            b.record(stream)
-        torch.cuda.synchronize()
-        kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+        kern_s = time_launches(stream, lambda: burst(state, edge, 0.0), args.kernel_reps)
         if args.calibrate_copy:
             calibration_copy(args.calibrate_copy)
     pts = info.n_points
@@ -979,14 +985,9 @@ def bench_upwind(args):
         for pts_, r_ in ((points, r), (2, 0.0), (3, 0.0), (4, 0.5)):
             if name(pts_, r_) in kern:
                 continue
-            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                   for _ in range(args.kernel_reps)]
-            for a, b in evs:
-                a.record(stream)
-                g.micro_burst_upwind(state, edge, 0.0, dt, n_t, pts_, r_)
-                b.record(stream)
-            torch.cuda.synchronize()
-            kern[name(pts_, r_)] = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+            kern[name(pts_, r_)] = time_launches(
+                stream, lambda: g.micro_burst_upwind(state, edge, 0.0, dt, n_t, pts_, r_),
+                args.kernel_reps)
         kern_s = kern[name(points, r)]
         g.sync()
         if args.calibrate_copy:
@@ -1355,27 +1356,21 @@ def main():
         g.sync()
         info = g.query()
         resident = bool(info.resident_solve)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.kernel_reps)]
         if resident:
             # Dominant kernel: the resident solve, one launch per 16-step replay (with its
             # table fill), timed with HIP events on the stream it runs on, per macro step.
-            for a, b in evs:
-                a.record(stream)
-                g.solve(U, n_steps=RESIDENT_STEPS)
-                b.record(stream)
-            torch.cuda.synchronize()
-            kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3 / RESIDENT_STEPS
+            kern_s = time_launches(stream, lambda: g.solve(U, n_steps=RESIDENT_STEPS),
+                                   args.kernel_reps) / RESIDENT_STEPS
         else:
             # Dominant kernel: the fused burst (pd_patch_step launches exactly that kernel),
             # timed with HIP events on the stream it runs on.
             V = torch.empty_like(U)
-            for k, (a, b) in enumerate(evs):
-                a.record(stream)
-                g.patch_step(U if k % 2 == 0 else V, t["t0"], out=V if k % 2 == 0 else U)
-                b.record(stream)
-            torch.cuda.synchronize()
-            kern_s = sum(a.elapsed_time(b) for a, b in evs) / len(evs) / 1e3
+            pair = [U, V]
+
+            def step():
+                g.patch_step(pair[0], t["t0"], out=pair[1])
+                pair.reverse()
+            kern_s = time_launches(stream, step, args.kernel_reps)
         g.sync()
         if args.calibrate_copy:
             # A plain streaming kernel of known traffic: read MIB MiB, write MIB MiB

@@ -13,6 +13,7 @@
 // tanh stretching clustered at x = 1, eq. (Transformation_Annulus) with xi = theta.
 // Source term k: T_k(t) (c_k S_k - L[S_k]), L the same operator applied to S_k.
 #include "pd_internal.h"
+#include "pd_refresh.h"
 
 namespace pdk {
 namespace {
@@ -304,6 +305,91 @@ __global__ void k_boundary(Geo g, const pd_coeff_desc* __restrict__ desc, double
   }
 }
 
+// Start time t_n + s0 dt of a sub-burst: one rounded product and one rounded sum (the
+// library is built without floating-point contraction), the value the host computes for
+// the same sub-burst, so its table equals the one a separate burst from there would use.
+__device__ double sub_burst_start(double t_n, int s0, double dt) {
+  return t_n + (double)s0 * dt;
+}
+
+// Time factors of the Q sub-bursts of a refreshed macro step: block row q fills sub-burst
+// q's table [ns][s1 - s0] at out + ns s0, one thread per entry.
+__global__ void k_refresh_tables(SrcInfo src, double t_n, double dt, int n_t, int Q,
+                                 double* __restrict__ out) {
+  const int q = blockIdx.y;
+  const int s0 = (int)((long long)n_t * q / Q), s1 = (int)((long long)n_t * (q + 1) / Q);
+  const int len = s1 - s0;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= src.ns * len) return;
+  const int j = e / len, s = e - j * len;
+  const double t_q = sub_burst_start(t_n, s0, dt);
+  out[(long long)src.ns * s0 + e] = time_factor(src, j, t_q + (double)s * dt);
+}
+
+// Blocks of the two refresh kernels below: the first RF_WAVES-patch groups restrict (one
+// wave per patch, as k_restrict), the blocks after them write the Dirichlet nodes.
+constexpr int RF_WAVES = 4;
+constexpr int RF_THREADS = 64 * RF_WAVES;
+
+__device__ double refresh_restrict(const Geo& g, const double* state, double* Ubar, int p,
+                                   int w, int lane, double (&rows)[RF_WAVES][64]) {
+  if (p < g.P && lane >= g.ls && lane < g.ls + g.nls)
+    rows[w][lane] = restriction_row(g, state, p, lane);
+  __syncthreads();
+  double v = 0.0;
+  if (p < g.P && lane == 0) {
+    v = restriction_total(g, rows[w]);
+    Ubar[p] = v;
+  }
+  return v;
+}
+
+__device__ void refresh_boundary(const Geo& g, const pd_coeff_desc& desc, double* U,
+                                 double t, int q) {
+  if (q >= boundary_count(g)) return;
+  int i, j;
+  boundary_node(g, q, i, j);
+  U[j * g.n_xi + i] = boundary_at(g, desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta, t);
+}
+
+__global__ __launch_bounds__(RF_THREADS) void k_refresh_field(
+    Geo g, const int* __restrict__ pmap, const pd_coeff_desc* __restrict__ desc,
+    const double* __restrict__ state, double* __restrict__ Ubar, double* __restrict__ U,
+    double t) {
+  __shared__ double rows[RF_WAVES][64];
+  const int groups = (g.P + RF_WAVES - 1) / RF_WAVES;
+  if ((int)blockIdx.x >= groups) {
+    refresh_boundary(g, *desc, U, t, ((int)blockIdx.x - groups) * RF_THREADS + threadIdx.x);
+    return;
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = blockIdx.x * RF_WAVES + w;
+  const double v = refresh_restrict(g, state, Ubar, p, w, lane, rows);
+  if (p < g.P && lane == 0) U[pmap[11 * p + 6]] = v;
+}
+
+__global__ __launch_bounds__(RF_THREADS) void k_refresh_final(
+    Geo g, const int* __restrict__ pmap, const pd_coeff_desc* __restrict__ desc,
+    const double* __restrict__ state, double* __restrict__ Ubar,
+    const double* __restrict__ U_n, double* __restrict__ U_np1, double dt_macro, double tau,
+    int* flag, double t) {
+  __shared__ double rows[RF_WAVES][64];
+  const int groups = (g.P + RF_WAVES - 1) / RF_WAVES;
+  if ((int)blockIdx.x >= groups) {
+    refresh_boundary(g, *desc, U_np1, t, ((int)blockIdx.x - groups) * RF_THREADS + threadIdx.x);
+    return;
+  }
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = blockIdx.x * RF_WAVES + w;
+  const double ub = refresh_restrict(g, state, Ubar, p, w, lane, rows);
+  if (p < g.P && lane == 0) {
+    const int node = pmap[11 * p + 6];
+    const double v = projective_value(U_n[node], ub, dt_macro, tau);
+    U_np1[node] = v;
+    if (!isfinite(v)) atomicOr(flag, 1);
+  }
+}
+
 // First node of a graph replay of S macro steps: macro steps base .. base+S-1 with base =
 // the clock's step count.  Fills the time factors of their bursts,
 // ttab[k][j][s] = T_j(t_n + s dt_micro) with t_n = t0 + (base + k) dt, and the Dirichlet
@@ -542,6 +628,36 @@ hipError_t launch_limits(const Geo& g, const pd_coeff_desc* dev_desc, int n_src,
 hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* U, double t,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_boundary, dim3(1), dim3(256), 0, s, g, dev_desc, U, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_tables(const SrcInfo& src, double t_n, double dt, int n_t, int Q,
+                                 double* out, hipStream_t s) {
+  if (src.ns == 0) return hipSuccess;
+  const int longest = (n_t + Q - 1) / Q;  // s1 - s0 <= ceil(n_t / Q)
+  const int bx = (src.ns * longest + 255) / 256;
+  hipLaunchKernelGGL(k_refresh_tables, dim3(bx, Q), dim3(256), 0, s, src, t_n, dt, n_t, Q, out);
+  return hipGetLastError();
+}
+
+static int refresh_blocks(const Geo& g) {
+  return (g.P + RF_WAVES - 1) / RF_WAVES + (boundary_count(g) + RF_THREADS - 1) / RF_THREADS;
+}
+
+hipError_t launch_refresh_field(const Geo& g, const int* pmap, const pd_coeff_desc* dev_desc,
+                                const double* state, double* Ubar, double* U, double t,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_field, dim3(refresh_blocks(g)), dim3(RF_THREADS), 0, s, g, pmap,
+                     dev_desc, state, Ubar, U, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_final(const Geo& g, const int* pmap, const pd_coeff_desc* dev_desc,
+                                const double* state, double* Ubar, const double* U_n,
+                                double* U_np1, double dt_macro, double tau, int* flag,
+                                double t, hipStream_t s) {
+  hipLaunchKernelGGL(k_refresh_final, dim3(refresh_blocks(g)), dim3(RF_THREADS), 0, s, g, pmap,
+                     dev_desc, state, Ubar, U_n, U_np1, dt_macro, tau, flag, t);
   return hipGetLastError();
 }
 

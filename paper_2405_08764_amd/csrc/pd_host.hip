@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "pd_internal.h"
+#include "pd_refresh.h"
 
 namespace pdk {
 #define PD_DECL(tag)                                                                      \
@@ -808,22 +809,29 @@ pd_status pd_macro_step_refresh(pd_grid g, const double* U_n, double* U_np1, dou
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(g->d.device));
   HIPCHK(launch_lift_bc(g->g, g->dpmap(), g->dtab(), U_n, state, edge, s));
+  // the time factors of every sub-burst in one launch (the sub-burst tables tile the
+  // n_t-step table's space, so the single-burst table cached on the grid is gone)
+  g->tt_ok = false;
+  HIPCHK(launch_refresh_tables(g->src, t_n, dt, n_t, n_refresh, g->ttab(), s));
   for (int q = 0; q < n_refresh; ++q) {
     const int s0 = (int)((long long)n_t * q / n_refresh);
     const int s1 = (int)((long long)n_t * (q + 1) / n_refresh);
-    if ((st = pd_micro_burst(g, state, edge, t_n + s0 * dt, dt, s1 - s0, stream))) return st;
+    BurstArgs a = base_args(g, t_n + s0 * dt, dt, s1 - s0);
+    a.state = state;
+    a.edge = edge;
+    a.ttab = g->ttab() + (size_t)g->src.ns * s0;
+    HIPCHK(launch_burst(g->d.precision, g->R, g->C, g->xch, MODE_SPLIT, a, g->blocks,
+                        g->threads, g->lds, s));
     if (q + 1 < n_refresh) {
-      // the macro field at the sub-burst's end: patch averages at the patch nodes,
-      // Dirichlet data on the boundary nodes; then eq. (edge) gradients from it
-      HIPCHK(launch_restrict(g->g, state, Ubar, s));
-      HIPCHK(launch_scatter_patch_values(g->g, g->dpmap(), Ubar, U_work, s));
-      HIPCHK(launch_boundary(g->g, g->ddesc(), U_work, t_n + s1 * dt, s));
+      // the macro field at the sub-burst's end (patch averages at the patch nodes,
+      // Dirichlet data on the boundary nodes), then eq. (edge) gradients from it
+      HIPCHK(launch_refresh_field(g->g, g->dpmap(), g->ddesc(), state, Ubar, U_work,
+                                  t_n + s1 * dt, s));
       HIPCHK(launch_lift_bc(g->g, g->dpmap(), g->dtab(), U_work, nullptr, edge, s));
     }
   }
-  HIPCHK(launch_restrict(g->g, state, Ubar, s));
-  HIPCHK(launch_macro_update(g->g, g->dpmap(), U_n, Ubar, U_np1, dt_macro, n_t * dt, g->flag(), s));
-  HIPCHK(launch_boundary(g->g, g->ddesc(), U_np1, t_n + dt_macro, s));
+  HIPCHK(launch_refresh_final(g->g, g->dpmap(), g->ddesc(), state, Ubar, U_n, U_np1, dt_macro,
+                              n_t * dt, g->flag(), t_n + dt_macro, s));
   return PD_OK;
 }
 

@@ -2,6 +2,7 @@
 // trapezoidal restriction and the projective update.  The fused hot path does the same
 // work inside the burst kernel; these exist so that each step can be checked on its own.
 #include "pd_internal.h"
+#include "pd_refresh.h"
 
 namespace pdk {
 namespace {
@@ -71,19 +72,10 @@ __global__ __launch_bounds__(64 * RS_WAVES) void k_restrict(Geo g,
   __shared__ double rows[RS_WAVES][64];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = blockIdx.x * RS_WAVES + w;
-  const int mx = g.m_xi, me = g.m_eta;
-  if (p < g.P && lane >= g.ls && lane < g.ls + g.nls) {
-    const double* u = state + (long long)p * mx * me + (long long)lane * mx;
-    double row = 0.0;
-    for (int k = g.ks; k < g.ks + g.nks; ++k) row += core_w(k, g.ks, g.nks) * u[k];
-    rows[w][lane] = row;
-  }
+  if (p < g.P && lane >= g.ls && lane < g.ls + g.nls)
+    rows[w][lane] = restriction_row(g, state, p, lane);
   __syncthreads();
-  if (p < g.P && lane == 0) {
-    double tot = 0.0;
-    for (int l = g.ls; l < g.ls + g.nls; ++l) tot += core_w(l, g.ls, g.nls) * rows[w][l];
-    Ubar[p] = tot / ((double)(g.nks - 1) * (double)(g.nls - 1));
-  }
+  if (p < g.P && lane == 0) Ubar[p] = restriction_total(g, rows[w]);
 }
 
 // Steps (v)-(vi) at the patch nodes.
@@ -93,8 +85,7 @@ __global__ void k_macro_update(Geo g, const int* __restrict__ pmap, const double
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= g.P) return;
   const int node = pmap[11 * p + 6];
-  const double F = (Ubar[p] - U[node]) / tau;
-  const double v = U[node] + dt_macro * F;
+  const double v = projective_value(U[node], Ubar[p], dt_macro, tau);
   Unew[node] = v;
   if (!isfinite(v)) atomicOr(flag, 1);
 }

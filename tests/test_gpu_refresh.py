@@ -94,3 +94,49 @@ def test_refresh_argument_checks(pd):
         g.macro_step_refresh(U, 0.0, 2, out=U)
     assert e.value.status == -1
 
+
+
+def patch_nodes(prob):
+    """Flat macro-node index of each patch, in patch order (rows of interior nodes; every
+    column when xi is periodic, the interior columns otherwise)."""
+    gd = prob["grid"]
+    nx, ne = gd["n_xi"], gd["n_eta"]
+    cols = range(nx) if gd["periodic_xi"] else range(1, nx - 1)
+    return torch.tensor([j * nx + i for j in range(1, ne - 1) for i in cols], device="cuda")
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_refresh_equals_its_stages(pd, name):
+    """The refresh step's combined kernels (the time factors of every sub-burst in one
+    launch; restriction, patch-node values and Dirichlet data in one launch; restriction,
+    projective step and Dirichlet data in one launch) against the same step built from the
+    separate entry points (lift, burst, restriction, boundary, projective step): bit for
+    bit, intermediate edge data included through the result."""
+    make, Q, _ = CASES[name]
+    prob = make()
+    g = pd.Grid(prob)
+    info = g.query()
+    t = prob["time"]
+    if t["dt_micro"] > 0.5 * info.dt_micro_limit or t["dt_macro"] > 0.5 * info.dt_macro_limit:
+        prob = W.fit_time(prob, info.dt_macro_limit, info.dt_micro_limit, 2)
+        g = pd.Grid(prob)
+        t = prob["time"]
+    dt, n_t = t["dt_micro"], t["n_t"]
+    tn = t["t0"] + 0.37 * t["dt_macro"]
+    U = g.initial(tn)
+    got = g.macro_step_refresh(U, tn, Q)
+    nodes = patch_nodes(prob)
+    assert nodes.numel() == info.n_patches
+    state, edge = g.lift_bc(U)
+    Uw = U.clone()
+    for q in range(Q):
+        s0, s1 = n_t * q // Q, n_t * (q + 1) // Q
+        g.micro_burst(state, edge, tn + s0 * dt, dt, s1 - s0)
+        if q + 1 < Q:
+            Uw.view(-1)[nodes] = g.restrict(state)
+            g.apply_boundary(Uw, tn + s1 * dt)
+            _, edge = g.lift_bc(Uw)
+    ref = g.macro_step(U, tn, Ubar=g.restrict(state))
+    g.sync()
+    say(name, "Q", Q, "max |diff| vs stages", float((got - ref).abs().max()))
+    assert torch.equal(got, ref)

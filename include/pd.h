@@ -284,7 +284,10 @@ pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
  * PD_OPT_RESIDENT_SOLVE (default 1): pd_solve runs each replay of its in-wave FP64 steps
  * as one launch whose waves stay resident across the steps (when they all fit on the
  * device at once and a patch block has at most 7 patches), else one launch per step;
- * the results are bitwise the same. */
+ * the results are bitwise the same.  The resident launch assumes the device is otherwise
+ * idle: if work on another stream holds the slots some of its waves need, their
+ * neighbours stop waiting after a bounded time and pd_sync returns PD_EDEVICE (turn the
+ * option off for grids that share the device with concurrent kernels). */
 #define PD_OPT_ALLOW_UNSTABLE 1
 #define PD_OPT_ROWS_PER_LANE 2
 #define PD_OPT_PATCHES_PER_BLOCK 3

@@ -44,6 +44,9 @@ CASES = {
                                       W.config1()["fields"], W.config1()["bc"],
                                       W.config1()["src"], W.timing(1e-3, 1, 2)), 25.0, 2),
     "sec411_m3": (lambda: W.paper_cdr(1, lam=0.1, n=6, m=3), None, 2),
+    # more than 64 nano steps: the register-line kernel evaluates the time factors in its
+    # step loop instead of tabulating them first
+    "config1_nt70": (lambda: W.config1(), 5.0, 70),
 }
 
 

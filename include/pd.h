@@ -283,7 +283,8 @@ pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
  * (0 = automatic).  Results do not depend on the launch shape (bitwise).
  * PD_OPT_RESIDENT_SOLVE (default 1): pd_solve runs each replay of its in-wave FP64 steps
  * as one launch whose waves stay resident across the steps (when they all fit on the
- * device at once and a patch block has at most 7 patches), else one launch per step;
+ * device at once, a patch block has at most 7 patches and at most one source term depends
+ * on time), else one launch per step;
  * the results are bitwise the same.  The resident launch assumes the device is otherwise
  * idle: if work on another stream holds the slots some of its waves need, their
  * neighbours stop waiting after a bounded time and pd_sync returns PD_EDEVICE (turn the

@@ -100,3 +100,19 @@ def test_resident_path_reported_on_graph_reuse(pd):
         assert g.query().resident_solve == resident
         out.append(U.cpu().numpy())
     assert np.array_equal(out[0], out[1])
+
+
+def test_two_time_sources_use_one_launch_per_step(pd):
+    """With two time-dependent source terms pd_solve keeps one launch per step (the
+    resident kernel is built for at most one) and reports it."""
+    c2 = W.config2(n=11, m=17)
+    src = list(c2["src"]) + [(("exp", 0.5, -1.0), -1.0, c2["src"][0][2])]
+    prob = W.problem(c2["grid"], c2["fields"], c2["bc"], src, c2["time"])
+    g = pd.Grid(prob)
+    assert g.query().n_time_sources == 2
+    g.set_option(pd.OPT_EXCHANGE, 2)
+    U = g.initial()
+    g.solve(U, n_steps=16)
+    g.sync()
+    assert g.query().resident_solve == 0
+    assert torch.isfinite(U).all()

@@ -56,8 +56,12 @@ def test_noalloc_gradients_equal_workspace_gradients(pd):
         assert np.isfinite(a).all()
         assert a.tobytes() == b.tobytes(), float(np.max(np.abs(a - b)))
         la, lb = loss.item(), l_ref.item()
-        say("  loss", la, lb)
-        assert np.isfinite(la) and abs(la - lb) <= 1e-6 * abs(lb)
+        # the loss is a sum of k = ceil(n / 4) non-negative block partials (one atomic add
+        # per block of 4 rows) taken in any order: each FP32 add errs by at most 2^-24 of a
+        # partial sum no larger than the total, so two orders differ by < 2 (k - 1) 2^-24
+        bound = 2 * (-(-n // 4) - 1) * 2.0 ** -24 * abs(lb)
+        say("  loss", la, lb, "bound", bound)
+        assert np.isfinite(la) and abs(la - lb) <= bound
 
 
 def test_noalloc_rejects_oversize_and_null(pd):

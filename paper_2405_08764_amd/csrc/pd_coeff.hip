@@ -312,18 +312,21 @@ __device__ double sub_burst_start(double t_n, int s0, double dt) {
   return t_n + (double)s0 * dt;
 }
 
-// Time factors of the Q sub-bursts of a refreshed macro step: block row q fills sub-burst
-// q's table [ns][s1 - s0] at out + ns s0, one thread per entry.
+// Time factors of the Q sub-bursts of a refreshed macro step, one thread per entry of the
+// ns n_t entries: sub-burst q's table [ns][s1 - s0] sits at out + ns s0, so entry E lies
+// in the sub-burst whose steps hold x = E / ns, i.e. the last q with floor(n_t q / Q) <= x.
 __global__ void k_refresh_tables(SrcInfo src, double t_n, double dt, int n_t, int Q,
                                  double* __restrict__ out) {
-  const int q = blockIdx.y;
+  const long long E = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (E >= (long long)src.ns * n_t) return;
+  const long long x = E / src.ns;
+  const int q = (int)(((x + 1) * Q - 1) / n_t);
   const int s0 = (int)((long long)n_t * q / Q), s1 = (int)((long long)n_t * (q + 1) / Q);
   const int len = s1 - s0;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= src.ns * len) return;
-  const int j = e / len, s = e - j * len;
+  const int r = (int)(E - (long long)src.ns * s0);
+  const int j = r / len, s = r - j * len;
   const double t_q = sub_burst_start(t_n, s0, dt);
-  out[(long long)src.ns * s0 + e] = time_factor(src, j, t_q + (double)s * dt);
+  out[E] = time_factor(src, j, t_q + (double)s * dt);
 }
 
 // Blocks of the two refresh kernels below: the first RF_WAVES-patch groups restrict (one
@@ -634,9 +637,8 @@ hipError_t launch_boundary(const Geo& g, const pd_coeff_desc* dev_desc, double* 
 hipError_t launch_refresh_tables(const SrcInfo& src, double t_n, double dt, int n_t, int Q,
                                  double* out, hipStream_t s) {
   if (src.ns == 0) return hipSuccess;
-  const int longest = (n_t + Q - 1) / Q;  // s1 - s0 <= ceil(n_t / Q)
-  const int bx = (src.ns * longest + 255) / 256;
-  hipLaunchKernelGGL(k_refresh_tables, dim3(bx, Q), dim3(256), 0, s, src, t_n, dt, n_t, Q, out);
+  const int blocks = (src.ns * n_t + 255) / 256;
+  hipLaunchKernelGGL(k_refresh_tables, dim3(blocks), dim3(256), 0, s, src, t_n, dt, n_t, Q, out);
   return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ CASES = {
     "annulus_Q5": (lambda: W.with_time(W.config3(n_r=9, n_theta=16, m=9), dt_macro=4e-4,
                                        n_t=23), 5, 3),
     "sine_cdr_Q4": (lambda: W.paper_cdr(2, lam=0.2, n=9, m=7, n_t=8, T=1e-3, n_steps=2), 4, 2),
+    "config1_Q11": (lambda: W.config1(n_t=11), 11, 2),  # one nano step per sub-burst
 }
 
 

@@ -751,13 +751,21 @@ def bench_refresh(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - s0
         g.sync()
-        # the dominant kernel: one sub-burst (split-mode burst), timed with HIP events
-        state, edge = g.lift_bc(U)
-        n_sub = t["n_t"] // Q
-        kern_s = time_launches(
-            stream, lambda: g.micro_burst(state, edge, t["t0"], t["dt_micro"], n_sub),
-            args.kernel_reps)
         info = g.query()
+        resident = bool(info.resident_refresh)
+        n_sub = t["n_t"] // Q
+        if resident:
+            # the dominant kernel: the resident refreshed step (k_refresh_x, one launch per
+            # macro step with its three small set-up launches), timed with HIP events
+            kern_s = time_launches(
+                stream, lambda: g.macro_step_refresh(U, t["t0"], Q, out=V), args.kernel_reps)
+        else:
+            # the dominant kernel: one sub-burst (split-mode burst), timed with HIP events
+            state, edge = g.lift_bc(U)
+            kern_s = time_launches(
+                stream, lambda: g.micro_burst(state, edge, t["t0"], t["dt_micro"], n_sub),
+                args.kernel_reps)
+        g.sync()
         if args.calibrate_copy:
             calibration_copy(args.calibrate_copy)
         # the frozen-edge fused step on the same problem (autotuned, graph replay)
@@ -774,10 +782,16 @@ def bench_refresh(args):
         t_fused = (time.perf_counter() - s0) / K
         gf.sync()
     per_step = W.updates_per_step(prob)
-    sub_updates = info.n_points * n_sub
-    achieved = 20 * sub_updates / kern_s
     shape = f"{info.exchange},{info.cols_per_lane},{info.rows_per_lane},{info.patches_per_block}"
-    traffic = read_traffic(KERNEL_NAME[info.exchange], "refresh", "f64", shape)
+    if resident:
+        achieved = 20 * per_step / kern_s
+        kname, kfiles = "k_refresh_x", SOLVE_SOURCES
+        ktxt = "k_refresh_x (resident: the whole refreshed step, set-up launches included)"
+    else:
+        achieved = 20 * info.n_points * n_sub / kern_s
+        kname, kfiles = KERNEL_NAME[info.exchange], None
+        ktxt = KERNEL_NAME[info.exchange] + " (split mode: one sub-burst)"
+    traffic = read_traffic(kname, "refresh", "f64", shape, kfiles)
     out = {
         "metric": "patch-point updates/s (and macro steps/s) with the edge data refreshed "
                   "during the burst",
@@ -797,10 +811,9 @@ def bench_refresh(args):
                               "block_threads": info.block_threads, "tuned_ms": tuned_ms}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK["f64"] / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK["f64"], "traffic": traffic,
-                     "kernel": KERNEL_NAME[info.exchange] + " (split mode: one sub-burst)",
-                     "kernel_ms": kern_s * 1e3, "flops_per_update": 20,
-                     "counters": read_counters(KERNEL_NAME[info.exchange], "refresh", "f64",
-                                               shape, kern_s)},
+                     "kernel": ktxt, "kernel_ms": kern_s * 1e3, "flops_per_update": 20,
+                     "counters": read_counters(kname, "refresh", "f64", shape, kern_s,
+                                               kfiles)},
         "frozen_edge_fused_ms_per_step": t_fused * 1e3,
     }
     if not args.no_cpu_baseline:
@@ -1267,7 +1280,7 @@ def main():
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
                  "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES,
-                 "k_solve_x": SOLVE_SOURCES}.get(kern)
+                 "k_solve_x": SOLVE_SOURCES, "k_refresh_x": SOLVE_SOURCES}.get(kern)
         counter_summary(args.counter_summary, args.counter_match or
                         kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                         args.counter_last, counter_file(kern, args.workload, args.precision),
@@ -1278,7 +1291,7 @@ def main():
         files = {"k_batch": BATCH_SOURCES, "k_closure_step": CLOSURE_SOURCES,
                  "k_burst_hux": HU_SOURCES, "k_burst_adi_r": ADI_SOURCES,
                  "k_burst_adi_hu": ADU_SOURCES, "k_fd_step": FD_SOURCES,
-                 "k_solve_x": SOLVE_SOURCES}.get(kern)
+                 "k_solve_x": SOLVE_SOURCES, "k_refresh_x": SOLVE_SOURCES}.get(kern)
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.counter_match or
                     kern + ("<" if kern.startswith("k_burst") or kern == "k_batch" else ""),
                     args.calibrate_copy or 256, traffic_file(kern, args.workload, args.precision),

@@ -140,6 +140,7 @@ typedef struct {
   int32_t tuned;             /* 1 once pd_autotune chose the launch shape               */
   double tuned_ms;           /* its measured time per fused step (ms), else 0           */
   int32_t resident_solve;    /* 1 if the last pd_solve ran resident launches           */
+  int32_t resident_refresh;  /* 1 if the last pd_macro_step_refresh ran resident       */
 } pd_info;
 
 typedef struct pd_grid_s* pd_grid;
@@ -246,8 +247,9 @@ pd_status pd_patch_step(pd_grid g, const double* U_n, double* U_np1, double t_n,
  * data at the next sub-burst's start time on the boundary nodes, and the eq. (edge)
  * gradients are recomputed from U_work.  Then (iv)-(vi) as pd_macro_step.  n_refresh = 1
  * is the split form of pd_macro_step.  Caller buffers: patch_state [P][m_eta][m_xi], edge
- * [P][4][M], Ubar [P], U_work [n_eta][n_xi] (distinct from U_n and U_np1).  PD_EINVAL
- * unless 1 <= n_refresh <= n_t; PD_EUNSTABLE as pd_macro_step. */
+ * [P][4][M], Ubar [P], U_work [n_eta][n_xi] (distinct from U_n and U_np1); their
+ * contents afterwards are unspecified.  PD_EINVAL unless 1 <= n_refresh <= n_t;
+ * PD_EUNSTABLE as pd_macro_step. */
 pd_status pd_macro_step_refresh(pd_grid g, const double* U_n, double* U_np1, double t_n,
                                 double dt_macro, double dt_micro, int32_t n_t,
                                 int32_t n_refresh, double* patch_state, double* edge,
@@ -285,7 +287,10 @@ pd_status pd_copy_coefficients(pd_grid g, double* dev_out, void* stream);
  * as one launch whose waves stay resident across the steps (when they all fit on the
  * device at once, a patch block has at most 7 patches and at most one source term depends
  * on time), else one launch per step;
- * the results are bitwise the same.  The resident launch assumes the device is otherwise
+ * the results are bitwise the same.  The same option lets pd_macro_step_refresh (n_refresh
+ * of 2 .. 16) run its sub-bursts in one such launch, the edge data refreshed between them
+ * through U_work and the workspace's second macro buffer (same results up to rounding
+ * order).  The resident launch assumes the device is otherwise
  * idle: if work on another stream holds the slots some of its waves need, their
  * neighbours stop waiting after a bounded time and pd_sync returns PD_EDEVICE (turn the
  * option off for grids that share the device with concurrent kernels). */

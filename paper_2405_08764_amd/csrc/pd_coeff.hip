@@ -329,6 +329,26 @@ __global__ void k_refresh_tables(SrcInfo src, double t_n, double dt, int n_t, in
   out[E] = time_factor(src, j, t_q + (double)s * dt);
 }
 
+// Set-up of a resident refreshed macro step: the Dirichlet values at the ends of sub-bursts
+// 0 .. Q - 2, out[q][nb] = u_b(t_n + s1 dt) with s1 = floor(n_t (q + 1) / Q) (the time
+// rounded as the host rounds it), row Q - 1 at t_end (the macro step's end), and the
+// waves' flags cleared.
+__global__ void k_refresh_setup(Geo g, const pd_coeff_desc* __restrict__ desc, double t_n,
+                                double dt, int n_t, int Q, double t_end,
+                                double* __restrict__ out, long long* __restrict__ flags,
+                                int nflags) {
+  const int nb = boundary_count(g);
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nflags) flags[e] = 0;
+  if (e >= (long long)Q * nb) return;
+  const int q = (int)(e / nb), b = (int)(e - (long long)q * nb);
+  const int s1 = (int)((long long)n_t * (q + 1) / Q);
+  int i, j;
+  boundary_node(g, b, i, j);
+  out[e] = boundary_at(g, *desc, g.xi0 + i * g.Dxi, g.eta0 + j * g.Deta,
+                       q + 1 < Q ? sub_burst_start(t_n, s1, dt) : t_end);
+}
+
 // Blocks of the two refresh kernels below: the first RF_WAVES-patch groups restrict (one
 // wave per patch, as k_restrict), the blocks after them write the Dirichlet nodes.
 constexpr int RF_WAVES = 4;
@@ -639,6 +659,17 @@ hipError_t launch_refresh_tables(const SrcInfo& src, double t_n, double dt, int 
   if (src.ns == 0) return hipSuccess;
   const int blocks = (src.ns * n_t + 255) / 256;
   hipLaunchKernelGGL(k_refresh_tables, dim3(blocks), dim3(256), 0, s, src, t_n, dt, n_t, Q, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh_setup(const Geo& g, const pd_coeff_desc* dev_desc, double t_n,
+                                double dt, int n_t, int Q, double t_end, double* out,
+                                long long* flags, int nflags, hipStream_t s) {
+  long long n = (long long)Q * boundary_count(g);
+  if (n < nflags) n = nflags;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refresh_setup, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+                     dev_desc, t_n, dt, n_t, Q, t_end, out, flags, nflags);
   return hipGetLastError();
 }
 

@@ -42,6 +42,11 @@ hipError_t launch_zero_flags(long long* f, int n, hipStream_t s);
 hipError_t launch_solve_x_f64(int R, int C, const BurstArgs& a, long long* flags, int* err,
                               int steps, const double* ttab0, const double* bval0, int per,
                               int blocks, size_t lds, hipStream_t s, int* resident);
+// Resident refreshed macro step with the in-wave exchange (pd_solve_x_f64.hip).
+size_t refresh_x_extra_lds(int ppb, int mx, int me, int nconst);
+hipError_t launch_refresh_x_f64(int R, int C, const BurstArgs& a, long long* flags, int* err,
+                                int Q, double* Uw0, double* Uw1, const double* bvq,
+                                int blocks, size_t lds, hipStream_t s, int* resident);
 
 // ADI burst with the higher-order upwind differences (pd_adi_upwind.hip): patches per
 // wave and LDS bytes for m_xi x m_eta patches (ppb = 0 when none fits), and the launcher.
@@ -155,7 +160,7 @@ struct pd_grid_s {
   double lim_micro = 0.0, lim_macro = 0.0;
   // options
   int allow_unstable = 0, opt_R = 0, opt_C = 0, opt_ppb = 0, opt_threads = 0, opt_xch = 0;
-  int opt_resident = 1, last_resident = 0;
+  int opt_resident = 1, last_resident = 0, last_refresh_resident = 0;
   // launch shape of the burst, fused and split mode alike
   int R = 0, C = 0, xch = 0, ppb = 0, threads = 0, blocks = 0;
   size_t lds = 0;
@@ -563,6 +568,7 @@ pd_status pd_query(pd_grid g, pd_info* out) {
   out->tuned = g->tuned;
   out->tuned_ms = g->tuned_ms;
   out->resident_solve = g->last_resident;
+  out->resident_refresh = g->last_refresh_resident;
   return PD_OK;
 }
 
@@ -808,6 +814,28 @@ pd_status pd_macro_step_refresh(pd_grid g, const double* U_n, double* U_np1, dou
   if ((st = guard_macro(g, dt_macro, dt, n_t))) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(g->d.device));
+  if (n_refresh > 1 && g->opt_resident && g->xch == XCH_LANES && g->d.precision == PD_F64 &&
+      g->threads == 64 && 9 * g->ppb <= 64 && g->src.ns <= 1 && n_refresh <= MAX_REPLAY) {
+    // every wave resident for the whole step: the sub-bursts in registers, the refreshed
+    // fields exchanged through U_work and the workspace's second macro buffer
+    HIPCHK(ensure_time_table(g, t_n, dt, n_t, s));
+    HIPCHK(launch_refresh_setup(g->g, g->ddesc(), t_n, dt, n_t, n_refresh, t_n + dt_macro,
+                                g->bvals(), g->pflags(), g->blocks, s));
+    BurstArgs a = base_args(g, t_n, dt, n_t);
+    a.U = U_n;
+    a.Unew = U_np1;
+    a.dt_macro = dt_macro;
+    a.tau = n_t * dt;
+    a.nb = boundary_count(g->g);  // row length of the Dirichlet table
+    int resident = 0;
+    HIPCHK(launch_refresh_x_f64(
+        g->R, g->C, a, g->pflags(), g->flag() + 1, n_refresh, U_work, g->V(), g->bvals(),
+        g->blocks, g->lds + refresh_x_extra_lds(g->ppb, g->g.m_xi, g->g.m_eta, g->src.nconst),
+        s, &resident));
+    g->last_refresh_resident = resident;
+    if (resident) return PD_OK;
+  }
+  g->last_refresh_resident = 0;
   HIPCHK(launch_lift_bc(g->g, g->dpmap(), g->dtab(), U_n, state, edge, s));
   // the time factors of every sub-burst in one launch (the sub-burst tables tile the
   // n_t-step table's space, so the single-burst table cached on the grid is gone)

@@ -39,6 +39,11 @@ __device__ inline double projective_value(double Un, double Ubar, double dt_macr
 // t_q = t_n + s0 dt, which is what one burst from t_q would read.
 hipError_t launch_refresh_tables(const SrcInfo& src, double t_n, double dt, int n_t, int Q,
                                  double* out, hipStream_t s);
+// Set-up of the resident refreshed step: Dirichlet values at the ends of sub-bursts
+// 0 .. Q - 2 (out[q][nb] at t_n + s1 dt) and at t_end (row Q - 1), flags[0 .. nflags) = 0.
+hipError_t launch_refresh_setup(const Geo& g, const pd_coeff_desc* dev_desc, double t_n,
+                                double dt, int n_t, int Q, double t_end, double* out,
+                                long long* flags, int nflags, hipStream_t s);
 // The macro field between two sub-bursts: every patch restricted (Ubar[p]), U at the
 // patch nodes set to those averages, U at the Dirichlet nodes set to u_b(t).
 hipError_t launch_refresh_field(const Geo& g, const int* pmap, const pd_coeff_desc* dev_desc,

@@ -84,7 +84,7 @@ class Info(C.Structure):
                 ("patches_per_block", C.c_int32), ("block_threads", C.c_int32),
                 ("cols_per_lane", C.c_int32), ("exchange", C.c_int32),
                 ("tuned", C.c_int32), ("tuned_ms", C.c_double),
-                ("resident_solve", C.c_int32)]
+                ("resident_solve", C.c_int32), ("resident_refresh", C.c_int32)]
 
 
 class BatchMember(C.Structure):

@@ -122,6 +122,7 @@ def test_refresh_equals_its_stages(pd, name):
         prob = W.fit_time(prob, info.dt_macro_limit, info.dt_micro_limit, 2)
         g = pd.Grid(prob)
         t = prob["time"]
+    g.set_option(pd.OPT_RESIDENT_SOLVE, 0)  # the separate-launch form
     dt, n_t = t["dt_micro"], t["n_t"]
     tn = t["t0"] + 0.37 * t["dt_macro"]
     U = g.initial(tn)
@@ -139,5 +140,48 @@ def test_refresh_equals_its_stages(pd, name):
             _, edge = g.lift_bc(Uw)
     ref = g.macro_step(U, tn, Ubar=g.restrict(state))
     g.sync()
+    assert g.query().resident_refresh == 0
     say(name, "Q", Q, "max |diff| vs stages", float((got - ref).abs().max()))
     assert torch.equal(got, ref)
+
+
+@pytest.mark.parametrize("Q", [2, 5, 16, 17])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_resident_refresh_equals_separate_launches(pd, name, Q):
+    """The resident refreshed step (one launch for all sub-bursts, the edge data exchanged
+    between waves) against the separate-launch form on the in-wave shape: the same up to
+    rounding order (the forcing moves by the change of the ghost terms instead of being
+    formed again from the state) over three steps; Q = 17 exceeds the resident form's
+    Dirichlet table and takes the separate launches."""
+    make, _, _ = CASES[name]
+    prob = make()
+    g0 = pd.Grid(prob)
+    info = g0.query()
+    t = prob["time"]
+    if t["dt_micro"] > 0.5 * info.dt_micro_limit or t["dt_macro"] > 0.5 * info.dt_macro_limit:
+        prob = W.fit_time(prob, info.dt_macro_limit, info.dt_micro_limit, 3)
+        t = prob["time"]
+    if Q > t["n_t"]:
+        prob = W.with_time(prob, n_t=Q + 3)
+        t = prob["time"]
+    out = []
+    for resident in (1, 0):
+        g = pd.Grid(prob)
+        try:
+            g.set_option(pd.OPT_EXCHANGE, 2)
+        except pd.PdError:
+            pytest.skip("no in-wave launch shape for this patch size")
+        if 9 * g.query().patches_per_block > 64:  # the resident form's limit: 7 per wave
+            g.set_option(pd.OPT_PATCHES_PER_BLOCK, 7)
+        g.set_option(pd.OPT_RESIDENT_SOLVE, resident)
+        U = g.initial()
+        V = g.new_U()
+        for s_ in range(3):
+            g.macro_step_refresh(U, t["t0"] + s_ * t["dt_macro"], Q, out=V)
+            U, V = V, U
+        g.sync()
+        assert g.query().resident_refresh == (1 if resident and Q <= 16 else 0)
+        out.append(U.cpu().numpy())
+    err = float(np.max(np.abs(out[0] - out[1]))) / max(1.0, float(np.max(np.abs(out[1]))))
+    say(name, "Q", Q, "resident vs separate", err)
+    assert err <= 1e-12, err

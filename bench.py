@@ -738,6 +738,8 @@ def bench_refresh(args):
             fix_shape(pd, g, args.shape)
         elif not args.no_autotune:
             tuned_ms = g.autotune(U, reps=5)
+        if args.no_resident:
+            g.set_option(pd.OPT_RESIDENT_SOLVE, 0)
         for s in range(args.warmup):
             g.macro_step_refresh(U, t["t0"] + s * t["dt_macro"], Q, out=V)
             U, V = V, U
@@ -1238,6 +1240,9 @@ def main():
     ap.add_argument("--shape", default=None,
                     help="force the launch shape 'exchange,cols,rows,patches_per_block' "
                          "(exchange 1 = LDS, 2 = in-wave); implies --no-autotune")
+    ap.add_argument("--no-resident", action="store_true",
+                    help="config1-3 and refresh: one launch per macro step (or per sub-burst) "
+                         "instead of the resident launches (PD_OPT_RESIDENT_SOLVE = 0)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (twice), the reference "
                          "kernel for scaling HBM byte counters")
@@ -1353,6 +1358,8 @@ def main():
             fix_shape(pd, g, args.shape)
         elif not args.no_autotune:
             tuned_ms = g.autotune(U, reps=5)
+        if args.no_resident:
+            g.set_option(pd.OPT_RESIDENT_SOLVE, 0)
         # set-up: one graph replay (16 steps) instantiates the solve graph on this field
         g.solve(U, n_steps=16)
         g.sync()
